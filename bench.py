@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the radiative hot path on one MI355X.
+
+Workload: the 8192-face open box (1 x 1 x 0.25 m at 1/64 m cells, multinomial
+MCRT noise of 1e4 rays per face, eps ~ U[0.1, 0.9], rho = 1 - eps).  One step
+is one pass of the whole hot path over that input, all on the GPU:
+
+  restore the noisy F -> iterative closure + reciprocity enforcement (FRACVAR,
+  until the closure defect is <= 1e-13) -> open-system Gebhart REF solve ->
+  REF closure / reciprocity residuals -> adjoint (dJ/d eps, dJ/d rho of the
+  net radiative loss to space) -> REF aggregation 8192 -> 2048 -> 128 nodes.
+
+It yields one REF matrix, so value = REF matrices per second.  The Gebhart
+solve is also timed alone in FP64 and in FP32 + FP64 refinement, each checked
+against the FP64 CPU oracle on the same enforced F (max |dB| must be
+<= 1e-10); the step uses the faster of the two that meets that bound.
+
+Prints one JSON line (see the keys at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense MFMA
+PEAK_HBM_GBS = 8000.0
+SIGMA = 5.67e-8
+T_SPACE = 3.0
+ENF_TOL = 1e-13
+ENF_MAX = 400
+ERR_BOUND = 1e-10
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def solve_flops(n: int) -> float:
+    """Algorithmic flops of B = K^{-1} E: LU (2/3 n^3) + two triangular solves on n+1 columns."""
+    return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * (n + 1)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["auto", "fp64", "fp32_ir"], default="auto")
+    ap.add_argument("--solve-reps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path - DESIGN.md describes how the solve would shard.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2511_04277_amd as rad
+    from paper_2511_04277_amd import _lib as L
+    from synth import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm device"
+    dev = torch.device("cuda:0")
+    lib = L.lib()
+
+    t0 = time.time()
+    inst = W.metric_workload()
+    n = inst.n
+    g1, g2 = inst.groups
+    n1, n2 = int(g1.max()) + 1, int(g2.max()) + 1
+    log(f"workload {inst.name}: n={n}, generated in {time.time() - t0:.1f}s")
+
+    def d(a, dt=torch.float64):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+    F0 = d(inst.f_noisy)
+    F = torch.empty_like(F0)
+    area, nrays, eps, rho = d(inst.area), d(inst.n_rays), d(inst.eps[0]), d(inst.rho[0])
+    w_ref = eps * area
+    grp1, grp2 = d(g1, torch.int32), d(g2, torch.int32)
+    # objective: net radiative loss to space of node temperatures (one per 4x4-face node)
+    rng = W.rng_for(8192, 1)
+    t_node = rng.uniform(200.0, 350.0, size=n2)
+    t_face = t_node[g2[g1]]
+    t4 = t_face ** 4
+    diff = np.empty((n, n + 1))
+    diff[:, :n] = t4[:, None] - t4[None, :]
+    diff[:, n] = t4 - T_SPACE ** 4
+    G = d(SIGMA * (inst.eps[0] * inst.area)[:, None] * diff)
+    del diff
+    Bbuf = torch.empty((n, n + 1), dtype=torch.float64, device=dev)
+    Y1 = torch.empty((n1, n1 + 1), dtype=torch.float64, device=dev)
+    Y2 = torch.empty((n2, n2 + 1), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    # ---- enforce once to get the F every solve below is fed with ----------
+    F.copy_(F0)
+    est = rad.enforce_vf_(F, area, nrays, kappa="fracvar", tol=ENF_TOL, max_iter=ENF_MAX)
+    log(f"enforcement: {est['iters']} iterations, closure defect {est['closure_defect']:.2e}, "
+        f"reciprocity error {est['recip_err']:.2e}")
+    F_enf_host = F.cpu().numpy()
+
+    # ---- Gebhart alone, both precisions ----------------------------------
+    solve = {}
+    factors = {}
+    for prec in ("fp64", "fp32_ir"):
+        B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf)
+        factors[prec] = fac
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.solve_reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf,
+                                         factors=fac)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        solve[prec] = {"ms": ms, "ref_per_s": 1000.0 / ms, "ir_steps": st.get("ir_steps", 0),
+                       "B": B.cpu().numpy()}
+        log(f"gebhart {prec}: {ms:.2f} ms  ({1000.0 / ms:.2f} REF/s), stats {st}")
+
+    # ---- oracle on the same enforced F: accuracy (and CPU baseline) -------
+    cpu = None
+    import oracle
+    t_orc = time.perf_counter()
+    b_ref = oracle.gebhart_ref(F_enf_host, inst.eps[0], inst.rho[0])
+    t_orc_solve = time.perf_counter() - t_orc
+    for prec in solve:
+        solve[prec]["max_abs_err"] = float(np.abs(solve[prec].pop("B") - b_ref).max())
+        log(f"gebhart {prec}: max|B - B_oracle| = {solve[prec]['max_abs_err']:.3e}")
+    ok = [p for p in solve if solve[p]["max_abs_err"] <= ERR_BOUND]
+    if args.precision != "auto":
+        prec = args.precision
+    else:
+        prec = min(ok or list(solve), key=lambda p: solve[p]["ms"])
+    for p in solve:
+        peak = PEAK_TFLOPS["fp64" if p == "fp64" else "fp32"]
+        solve[p]["solve_tflops"] = solve_flops(n) / (solve[p]["ms"] * 1e-3) / 1e12
+        solve[p]["lu_mfma_frac_of_peak"] = solve[p]["solve_tflops"] / peak
+
+    # ---- the step ---------------------------------------------------------
+    fac = factors[prec]
+
+    def step():
+        F.copy_(F0)
+        rad.enforce_vf_(F, area, nrays, kappa="fracvar", tol=ENF_TOL, max_iter=ENF_MAX, want_stats=False)
+        B, _, _ = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf,
+                                  factors=fac, want_stats=False)
+        chk = rad.ref_check(B, eps, area)
+        ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, F, rho, B, G, ir_tol=1e-12, ir_max=4, want_stats=False)
+        y1, w1 = rad.aggregate_nodes(B, w_ref, grp1, n1, out=Y1, validate=False)
+        y2, _ = rad.aggregate_nodes(y1, w1, grp2, n2, out=Y2, validate=False)
+        return chk, ge, gr, y2
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lib.rad_profile_enable(1)
+    lib.rad_profile_read((L.RadKernelProfile * 5)(), 5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        chk, ge, gr, y2 = step()
+    e1.record()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    profs = (L.RadKernelProfile * 5)()
+    L.check(lib.rad_profile_read(profs, 5), "rad_profile_read")
+    lib.rad_profile_enable(0)
+    ms_step = total_ms / args.steps
+    chk_h = chk.cpu().numpy()
+    kern = {}
+    for k, name in enumerate(L.PROFILE_KINDS):
+        p = profs[k]
+        if p.launches:
+            kern[name] = {"launches": int(p.launches), "avg_us": 1000.0 * p.total_ms / p.launches,
+                          "total_ms_per_step": p.total_ms / args.steps,
+                          "tflops": (p.flops / (p.total_ms * 1e-3) / 1e12) if p.flops else None,
+                          "gbs": (p.bytes / (p.total_ms * 1e-3) / 1e9) if p.bytes else None}
+    dom = "gemm_f64" if prec == "fp64" else "gemm_f32"
+    pk = profs[L.PROFILE_KINDS.index(dom)]
+    achieved = pk.flops / pk.launches / (pk.total_ms / pk.launches * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["fp64" if dom == "gemm_f64" else "fp32"]
+    roofline = {"bound": "mfma", "kernel": f"gemm_mfma<{'double' if dom == 'gemm_f64' else 'float'}>",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+    sw = profs[L.PROFILE_KINDS.index("enforce_sweep")]
+    if sw.launches:
+        kern["enforce_sweep"]["hbm_frac"] = (sw.bytes / (sw.total_ms * 1e-3) / 1e9) / PEAK_HBM_GBS
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same step ----
+    if not args.no_cpu_baseline:
+        import threadpoolctl
+        threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
+        f_in = inst.f_noisy
+        k_iter = 2
+        t = time.perf_counter()
+        oracle.enforce_vf(f_in, inst.area, inst.n_rays, "fracvar", tol=0.0, max_iter=k_iter)
+        t_enf_iter = (time.perf_counter() - t) / k_iter
+        gnp = G.cpu().numpy()
+        t = time.perf_counter()
+        oracle.gebhart_ref_adjoint(F_enf_host, inst.eps[0], inst.rho[0], b_ref, gnp)
+        t_adj = time.perf_counter() - t
+        t = time.perf_counter()
+        y1h, w1h = oracle.aggregate_nodes(b_ref, inst.eps[0] * inst.area, g1, n1)
+        oracle.aggregate_nodes(y1h, w1h, g2, n2)
+        t_agg = time.perf_counter() - t
+        s_cpu = t_enf_iter * est["iters"] + t_orc_solve + t_adj + t_agg
+        cpu = {"value": 1.0 / s_cpu, "unit": "REF matrices/s", "cores": int(threads), "kind": "oracle",
+               "sample": (f"one step's parts on the n={n} input: {k_iter} of {est['iters']} enforcement "
+                          f"iterations timed and scaled ({t_enf_iter:.2f} s each), the REF solve "
+                          f"({t_orc_solve:.1f} s, LAPACK getrf/getrs), the adjoint ({t_adj:.1f} s) and the "
+                          f"two-level aggregation ({t_agg:.1f} s), each timed once"),
+               "seconds_per_step": s_cpu, "host_cpus": os.cpu_count()}
+        log(f"cpu baseline: {s_cpu:.1f} s per step on {threads} BLAS threads")
+
+    out = {
+        "metric": "REF matrices/sec at N=8192, mixed-prec vs FP64 LU at <=1e-10 err; LU MFMA %",
+        "value": 1000.0 / ms_step,
+        "unit": "REF matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "open_box_n8192 (1x1x0.25 m, 1/64 m cells, 1e4 rays/face) full pipeline",
+                   "n": n, "precision": prec, "kappa": "fracvar", "enforce_tol": ENF_TOL,
+                   "enforce_iters": est["iters"], "aggregation": f"{n}->{n1}->{n2}",
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "gebhart_solve": solve,
+        "kernels": kern,
+        "ref_residuals": {"closure": float(chk_h[0]), "reciprocity": float(chk_h[1])},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

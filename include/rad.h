@@ -1,0 +1,227 @@
+/*
+ * rad.h - C ABI of the gfx950 radiative hot path.
+ *
+ * Data-parallel core of the radiative pipeline of B. Frangi, "Novel Numerical
+ * Methods for Accurate Space Thermal Analysis" (arXiv:2511.04277):
+ *
+ *   noisy MCRT view factors F  --rad_enforce_vf-->  F satisfying closure and
+ *   reciprocity  --rad_gebhart_ref-->  REF matrix B  --rad_aggregate_nodes-->
+ *   face / node level factors,  plus  rad_gebhart_ref_adjoint  (dJ/d eps, rho).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Open-system matrices are N x (N+1), row-major, float64, leading dimension
+ *   ld >= N+1 (in elements); column N is deep space (thesis Sec. 2.4.12, the
+ *   N x (N+1) layout of the open-system view-factor matrix).
+ * - Every array argument is a DEVICE pointer unless marked "host".  The caller
+ *   owns all memory: the library never allocates or frees device memory inside
+ *   a call; scratch comes from the caller's ``work`` buffer, whose size is
+ *   given by the matching *_workspace_bytes() query (256-byte alignment).
+ * - ``stream`` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *   work on it and return.  When ``stats`` (host) is non-NULL the call waits
+ *   for its own work and fills it; device-side errors (non-finite or
+ *   out-of-range input, zero row, singular pivot) are only reported then.
+ * - Return value: RAD_OK (0), a positive warning, or a negative error code;
+ *   rad_last_error() gives a message for the calling thread.  No exception
+ *   crosses the ABI.  On an error the outputs are unspecified.
+ * - Calls on the same stream are ordered; calls that share a workspace on
+ *   different streams race.
+ */
+#ifndef RAD_H
+#define RAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RAD_OK 0
+#define RAD_WNOTCONVERGED 1   /* tol > 0 not met within max_iter / ir_max   */
+#define RAD_EINVAL (-1)       /* bad size, stride, mode or NULL pointer      */
+#define RAD_ENONFINITE (-2)   /* NaN/Inf or out-of-range value in an input   */
+#define RAD_EZEROROW (-3)     /* a view-factor row sums to zero              */
+#define RAD_ESINGULAR (-4)    /* a pivot block of K is singular              */
+#define RAD_EHIP (-5)         /* a HIP runtime call failed                   */
+#define RAD_EWORKSPACE (-6)   /* work / factor buffer too small or misaligned */
+
+/* ---- options ----------------------------------------------------------- */
+#define RAD_KAPPA_FRACVAR 0   /* fractional-variance weight, eq. 3.23-3.25  */
+#define RAD_KAPPA_HALF 1      /* equal weights kappa = 1/2 (eq. 3.20)        */
+
+#define RAD_PREC_FP64 0       /* FP64 MFMA factorization and solves          */
+#define RAD_PREC_FP32_IR 1    /* FP32 MFMA factorization and solves, FP64
+                                 residual iterative refinement               */
+
+/* Per-call statistics (host struct). */
+typedef struct rad_stats {
+  int32_t iters;          /* enforcement iterations executed                 */
+  int32_t ir_steps;       /* iterative-refinement steps executed             */
+  int32_t converged;      /* 1 if the tolerance was met                      */
+  int32_t device_status;  /* status raised by device-side checks (0 = ok)    */
+  double closure_defect;  /* max_i |s_i - 1| after the last reciprocity step */
+  double recip_err;       /* max|eta_ij - eta_ji| / max eta entering the last
+                             iteration (eta_ij = A_i F_ij)                   */
+  double ir_correction;   /* max |delta B| of the last refinement step       */
+  double ir_residual;     /* max |E - K B| before the last refinement step   */
+} rad_stats;
+
+const char* rad_status_string(int32_t code);
+const char* rad_last_error(void);
+int32_t rad_version(void);
+
+/* ---- iterative closure + reciprocity enforcer ------------------------- */
+/*
+ * Thesis Sec. 3.5.5 ("Iterative closure and reciprocity enforcer"), applied
+ * in place to F (n x (n+1), ld ldf).  Each iteration:
+ *   1. reciprocity on the square block, i != j (Sec. 3.5.3, eq. 3.18-3.20):
+ *      eta_ij = A_i F_ij, eta^ = kappa eta_ij + (1-kappa) eta_ji, used for
+ *      both F_ij = eta^/A_i and F_ji = eta^/A_j; kappa by ``kappa_mode``:
+ *      RAD_KAPPA_FRACVAR: kappa = s2_ji / (s2_ij + s2_ji),
+ *      s2_ij = A_i^2 (1 - F_ij) / (n_rays_i F_ij) (eq. 3.23-3.25; z cancels;
+ *      a zero factor gets all weight moved to its partner; both zero -> 1/2);
+ *      RAD_KAPPA_HALF: kappa = 1/2 (reproduces the worked example, Sec. 6.2).
+ *      The diagonal and the space column are carried over unchanged.
+ *   2. closure over all n+1 columns by least-squares smoothing for open
+ *      systems with omega = eta (Sec. 3.5.4, eq. 3.36-3.40): F_ij /= s_i,
+ *      s_i = sum_j F_ij.
+ * Stopping: with tol > 0 the loop ends after the first iteration whose
+ * closure defect max_i |s_i - 1| is <= tol (returns RAD_WNOTCONVERGED if
+ * max_iter is reached first); tol == 0 runs exactly max_iter iterations and
+ * needs no host synchronisation (graph-capturable when stats == NULL).
+ *
+ * area:   n face areas A_i > 0.
+ * n_rays: n rays emitted per face (> 0); may be NULL for RAD_KAPPA_HALF.
+ * work:   >= rad_enforce_workspace_bytes(n).
+ * Device checks: F entries finite and >= 0 (RAD_ENONFINITE), zero rows
+ * (RAD_EZEROROW).
+ */
+size_t rad_enforce_workspace_bytes(int64_t n);
+int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const double* area,
+                       const double* n_rays, int32_t kappa_mode, double tol,
+                       int32_t max_iter, void* work, size_t work_bytes,
+                       rad_stats* stats, void* stream);
+
+/* ---- open-system Gebhart REF solve ------------------------------------- */
+/*
+ * Gebhart's matrix method extended to open systems (Sec. 4.2.3, eq. 4.5;
+ * App. B.2, eq. B.6-B.11):
+ *   K = I - F_sq diag(rho)  (n x n),   E = [F_sq diag(eps) | F_space],
+ *   B = K^{-1} E            (n x (n+1), written to B with ld ldb).
+ * eps, rho: n values in [0, 1] (independent inputs; rho = 1 - eps for gray
+ * opaque faces).  K is strictly diagonally dominant by rows when rho < 1 and
+ * the rows of F sum to <= 1, so the factorization is a block LU without
+ * pivoting.
+ * precision: RAD_PREC_FP64, or RAD_PREC_FP32_IR (FP32 factorization/solves,
+ *   refinement B += K^{-1}(E - K B) with the residual in FP64 until
+ *   max|delta| <= ir_tol or ir_max steps; RAD_WNOTCONVERGED otherwise).
+ * factors: caller-owned, >= rad_gebhart_factor_bytes(n, precision); receives
+ *   the factorization, which rad_gebhart_ref_adjoint reuses.  It stays valid
+ *   until the caller frees or overwrites it.
+ * work: >= rad_gebhart_workspace_bytes(n, precision).
+ * Device checks: eps, rho outside [0, 1] or non-finite, non-finite F
+ *   (RAD_ENONFINITE); a pivot below 1e-11 (FP64) / 1e-5 (FP32) in the
+ *   elimination, i.e. a numerically singular K (RAD_ESINGULAR).
+ */
+size_t rad_gebhart_factor_bytes(int64_t n, int32_t precision);
+size_t rad_gebhart_workspace_bytes(int64_t n, int32_t precision);
+int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf,
+                        const double* eps, const double* rho, double* B,
+                        int64_t ldb, int32_t precision, double ir_tol,
+                        int32_t ir_max, void* factors, size_t factor_bytes,
+                        void* work, size_t work_bytes, rad_stats* stats,
+                        void* stream);
+
+/*
+ * REF relations as residuals (Sec. 4.2.1, eq. 4.3-4.4), computed in FP64:
+ *   out[0] = max_i |sum_{j<=n} B_ij + B_i,space - 1|            (closure)
+ *   out[1] = max_{i,j} |eps_i A_i B_ij - eps_j A_j B_ji|        (reciprocity)
+ * out: 2 doubles (device).  work: >= rad_ref_check_workspace_bytes(n).
+ */
+size_t rad_ref_check_workspace_bytes(int64_t n);
+int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const double* eps,
+                      const double* area, double* out, void* work,
+                      size_t work_bytes, void* stream);
+
+/* ---- adjoint of the REF solve ------------------------------------------ */
+/*
+ * Given G = dJ/dB (n x (n+1), ld ldg) for the B computed by rad_gebhart_ref
+ * with the same F, rho, ``factors`` and ``precision``:
+ *   Lambda = K^{-T} G                       (transposed solve, factors reused;
+ *                                            FP64 refinement in FP32_IR mode)
+ *   grad_eps[k] = sum_i Lambda_ik F_ik
+ *   grad_rho[k] = sum_i sum_j F_ik Lambda_ij B_kj
+ *               = (1/rho_k) sum_j B_kj (Lambda_kj - G_kj)  (K^T Lambda = G),
+ *     the direct column form being used where rho_k < 1e-3.
+ * These are the derivatives through B only (B = K^{-1}E, App. B.2); an
+ * objective with explicit eps/rho terms adds its own partials.
+ * Lambda (nullable, ld ldl) receives K^{-T} G when non-NULL.
+ * In RAD_PREC_FP32_IR the transposed solve is refined in FP64 (residual
+ * G - K^T Lambda) until max|delta| <= ir_tol or ir_max steps.
+ * work: >= rad_adjoint_workspace_bytes(n, precision).
+ */
+size_t rad_adjoint_workspace_bytes(int64_t n, int32_t precision);
+int32_t rad_gebhart_ref_adjoint(const void* factors, size_t factor_bytes,
+                                int32_t precision, const double* F, int64_t n,
+                                int64_t ldf, const double* rho, const double* B,
+                                int64_t ldb, const double* G, int64_t ldg,
+                                double* grad_eps, double* grad_rho, double* Lambda,
+                                int64_t ldl, double ir_tol, int32_t ir_max,
+                                void* work, size_t work_bytes, rad_stats* stats,
+                                void* stream);
+
+/* ---- multi-node aggregation -------------------------------------------- */
+/*
+ * Surface / node factors from sub-surface factors (Sec. 5.2.3, eq. 5.6-5.7;
+ * first two rows of eq. 5.28, one-sided faces):
+ *   Y_GH = sum_{i in G} sum_{j in H} w_i X_ij / W_G,
+ *   Y_G,space = sum_{i in G} w_i X_i,space / W_G,   W_G = sum_{i in G} w_i.
+ * X: n x (n+1) (ld ldx); weight: n values > 0 (w_i = S_i for view factors,
+ * eps_i S_i for REFs); group: n int32 in [0, g) (device); Y: g x (g+1)
+ * (ld ldy); group_weight: g doubles receiving W_G (nullable).  Every group
+ * must be non-empty and every id in range; these are checked on the device
+ * and reported (RAD_EINVAL) when ``stats`` is non-NULL.  Sums run in a fixed
+ * order (bitwise reproducible).
+ * work: >= rad_aggregate_workspace_bytes(n, g).
+ */
+size_t rad_aggregate_workspace_bytes(int64_t n, int64_t g);
+int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
+                            const double* weight, const int32_t* group,
+                            int64_t g, double* Y, int64_t ldy,
+                            double* group_weight, void* work, size_t work_bytes,
+                            rad_stats* stats, void* stream);
+
+/* ---- kernel profiling --------------------------------------------------- */
+/*
+ * Optional per-launch timing with HIP events, for measuring the hot kernels
+ * against their rooflines.  rad_profile_enable(1) makes the calling host
+ * thread bracket every launch of the kernels below with two events on the
+ * launch's stream; rad_profile_read waits for the recorded events, writes
+ * per-kind totals into out[0..count) and resets them.  flops / bytes are the
+ * algorithmic work of the launches (2 M N K for a GEMM; one read and one write
+ * of the n x (n+1) matrix for an enforcement sweep; one read of it for an
+ * aggregation).  Profiling adds two event records per launch.
+ */
+#define RAD_PROF_GEMM_F64 0      /* FP64 MFMA GEMM (factorization, solves, residual) */
+#define RAD_PROF_GEMM_F32 1      /* FP32 MFMA GEMM                                   */
+#define RAD_PROF_ENFORCE_SWEEP 2 /* enforcement sweep                                */
+#define RAD_PROF_DIAG_INVERSE 3  /* Gauss-Jordan inverse of a diagonal block         */
+#define RAD_PROF_AGGREGATE 4     /* aggregation reduction                            */
+#define RAD_PROF_KINDS 5
+
+typedef struct rad_kernel_profile {
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} rad_kernel_profile;
+
+int32_t rad_profile_enable(int32_t on);
+int32_t rad_profile_read(rad_kernel_profile* out, int32_t count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAD_H */

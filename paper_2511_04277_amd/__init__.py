@@ -1,0 +1,12 @@
+"""gfx950 (MI355X) implementation of the radiative hot path of arXiv:2511.04277.
+
+The compute lives in ``librad.so`` (hand-written HIP, C ABI in include/rad.h);
+this package is its Python binding.  Importing it does not need a GPU; calling
+an operation needs the built library and a ROCm device.
+"""
+from . import _lib
+from .api import (Factors, GebhartREF, aggregate_nodes, enforce_vf_, gebhart_ref,
+                  gebhart_ref_adjoint, ref_check)
+
+__all__ = ["Factors", "GebhartREF", "aggregate_nodes", "enforce_vf_", "gebhart_ref",
+           "gebhart_ref_adjoint", "ref_check", "_lib"]

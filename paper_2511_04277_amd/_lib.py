@@ -1,0 +1,116 @@
+"""ctypes binding of librad.so (the C ABI declared in include/rad.h).
+
+Argument marshalling only.  The library must have been built
+(``python -m paper_2511_04277_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import pathlib
+
+_PKG = pathlib.Path(__file__).resolve().parent
+LIB_PATH = pathlib.Path(os.environ.get("RAD_LIBRARY", _PKG / "librad.so"))
+
+RAD_OK = 0
+RAD_WNOTCONVERGED = 1
+RAD_EINVAL = -1
+RAD_ENONFINITE = -2
+RAD_EZEROROW = -3
+RAD_ESINGULAR = -4
+RAD_EHIP = -5
+RAD_EWORKSPACE = -6
+
+RAD_KAPPA_FRACVAR = 0
+RAD_KAPPA_HALF = 1
+RAD_PREC_FP64 = 0
+RAD_PREC_FP32_IR = 1
+
+
+class RadStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("ir_steps", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("device_status", ctypes.c_int32),
+        ("closure_defect", ctypes.c_double),
+        ("recip_err", ctypes.c_double),
+        ("ir_correction", ctypes.c_double),
+        ("ir_residual", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class RadKernelProfile(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
+PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate"]
+
+
+class RadError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {code}: {msg}")
+        self.code = code
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+_STATS = ctypes.POINTER(RadStats)
+
+# name -> (restype, argtypes); mirrors include/rad.h
+SIGNATURES = {
+    "rad_status_string": (ctypes.c_char_p, [_I32]),
+    "rad_last_error": (ctypes.c_char_p, []),
+    "rad_version": (_I32, []),
+    "rad_enforce_workspace_bytes": (_SZ, [_I64]),
+    "rad_enforce_vf": (_I32, [_P, _I64, _I64, _P, _P, _I32, _D, _I32, _P, _SZ, _STATS, _P]),
+    "rad_gebhart_factor_bytes": (_SZ, [_I64, _I32]),
+    "rad_gebhart_workspace_bytes": (_SZ, [_I64, _I32]),
+    "rad_gebhart_ref": (_I32, [_P, _I64, _I64, _P, _P, _P, _I64, _I32, _D, _I32, _P, _SZ, _P, _SZ, _STATS, _P]),
+    "rad_ref_check_workspace_bytes": (_SZ, [_I64]),
+    "rad_ref_check": (_I32, [_P, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "rad_adjoint_workspace_bytes": (_SZ, [_I64, _I32]),
+    "rad_gebhart_ref_adjoint": (_I32, [_P, _SZ, _I32, _P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P,
+                                      _I64, _D, _I32, _P, _SZ, _STATS, _P]),
+    "rad_aggregate_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_aggregate_nodes": (_I32, [_P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _SZ, _STATS, _P]),
+    "rad_profile_enable": (_I32, [_I32]),
+    "rad_profile_read": (_I32, [ctypes.POINTER(RadKernelProfile), _I32]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librad.so once; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2511_04277_amd.build`")
+        l = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(l, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def check(code: int, where: str) -> int:
+    if code < 0:
+        msg = lib().rad_last_error().decode() or lib().rad_status_string(code).decode()
+        raise RadError(code, where, msg)
+    return code

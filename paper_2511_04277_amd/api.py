@@ -1,0 +1,207 @@
+"""PyTorch-facing wrappers of the C ABI (include/rad.h).
+
+Torch supplies device memory and the current HIP stream; every step of the
+computation runs in librad's HIP kernels.  Matrices are float64 CUDA tensors
+of shape (N, N+1) whose rows may be padded (``stride(0) >= N+1``,
+``stride(1) == 1``).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib as L
+
+_KAPPA = {"fracvar": L.RAD_KAPPA_FRACVAR, "half": L.RAD_KAPPA_HALF}
+_PREC = {"fp64": L.RAD_PREC_FP64, "fp32_ir": L.RAD_PREC_FP32_IR}
+
+
+def _vp(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _mat(t: torch.Tensor, name: str, rows: Optional[int] = None, cols: Optional[int] = None) -> int:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+        raise ValueError(f"{name}: expected a 2-D float64 CUDA tensor with unit column stride")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name}: expected {rows} rows, got {t.shape[0]}")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name}: expected {cols} columns, got {t.shape[1]}")
+    return t.stride(0) if t.shape[0] > 1 else max(t.stride(0), t.shape[1])
+
+
+def _vec(t: Optional[torch.Tensor], name: str, n: int, dtype=torch.float64):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.dim() == 1 and t.shape[0] == n and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous {dtype} CUDA vector of length {n}")
+    return t
+
+
+class _Workspace:
+    """Per-device scratch buffers, grown on demand and reused across calls."""
+
+    def __init__(self):
+        self._bufs = {}
+
+    def get(self, device: torch.device, key: str, nbytes: int) -> torch.Tensor:
+        k = (device.index, key)
+        buf = self._bufs.get(k)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+            self._bufs[k] = buf
+        return buf
+
+
+WORKSPACE = _Workspace()
+
+
+def enforce_vf_(F: torch.Tensor, area: torch.Tensor, n_rays: Optional[torch.Tensor] = None,
+                kappa: str = "fracvar", tol: float = 0.0, max_iter: int = 100,
+                want_stats: bool = True) -> dict:
+    """In-place iterative closure + reciprocity enforcement (Sec. 3.5.5)."""
+    n = F.shape[0]
+    ld = _mat(F, "F", n, n + 1)
+    _vec(area, "area", n)
+    _vec(n_rays, "n_rays", n)
+    lib = L.lib()
+    wb = lib.rad_enforce_workspace_bytes(n)
+    work = WORKSPACE.get(F.device, "enforce", wb)
+    st = L.RadStats()
+    code = lib.rad_enforce_vf(_vp(F), n, ld, _vp(area), _vp(n_rays), _KAPPA[kappa], float(tol),
+                              int(max_iter), _vp(work), work.numel(),
+                              ctypes.byref(st) if want_stats else None, _stream(F.device))
+    L.check(code, "rad_enforce_vf")
+    out = st.as_dict() if want_stats else {}
+    out["status"] = code
+    return out
+
+
+def aggregate_nodes(X: torch.Tensor, weight: torch.Tensor, group: torch.Tensor, g: int,
+                    out: Optional[torch.Tensor] = None, validate: bool = True) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Y_GH = sum_{i in G, j in H} w_i X_ij / W_G (eq. 5.6-5.7); returns (Y, W)."""
+    n = X.shape[0]
+    ldx = _mat(X, "X", n, n + 1)
+    _vec(weight, "weight", n)
+    _vec(group, "group", n, torch.int32)
+    if out is None:
+        out = torch.empty((g, g + 1), dtype=torch.float64, device=X.device)
+    ldy = _mat(out, "Y", g, g + 1)
+    gw = torch.empty(g, dtype=torch.float64, device=X.device)
+    lib = L.lib()
+    wb = lib.rad_aggregate_workspace_bytes(n, g)
+    work = WORKSPACE.get(X.device, "aggregate", wb)
+    st = L.RadStats()
+    code = lib.rad_aggregate_nodes(_vp(X), n, ldx, _vp(weight), _vp(group), int(g), _vp(out), ldy,
+                                   _vp(gw), _vp(work), work.numel(),
+                                   ctypes.byref(st) if validate else None, _stream(X.device))
+    L.check(code, "rad_aggregate_nodes")
+    return out, gw
+
+
+class Factors:
+    """Device buffer holding a factorization of K (reused by the adjoint)."""
+
+    def __init__(self, n: int, precision: str, device: torch.device):
+        self.n = n
+        self.precision = precision
+        nbytes = L.lib().rad_gebhart_factor_bytes(n, _PREC[precision])
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def gebhart_ref(F: torch.Tensor, eps: torch.Tensor, rho: torch.Tensor, precision: str = "fp64",
+                ir_tol: float = 1e-12, ir_max: int = 4, out: Optional[torch.Tensor] = None,
+                factors: Optional[Factors] = None, want_stats: bool = True):
+    """B = K^{-1} E (App. B.2, eq. B.8-B.11).  Returns (B, factors, stats)."""
+    n = F.shape[0]
+    ldf = _mat(F, "F", n, n + 1)
+    _vec(eps, "eps", n)
+    _vec(rho, "rho", n)
+    if out is None:
+        out = torch.empty((n, n + 1), dtype=torch.float64, device=F.device)
+    ldb = _mat(out, "B", n, n + 1)
+    if factors is None or factors.n != n or factors.precision != precision:
+        factors = Factors(n, precision, F.device)
+    lib = L.lib()
+    p = _PREC[precision]
+    work = WORKSPACE.get(F.device, "gebhart", lib.rad_gebhart_workspace_bytes(n, p))
+    st = L.RadStats()
+    code = lib.rad_gebhart_ref(_vp(F), n, ldf, _vp(eps), _vp(rho), _vp(out), ldb, p, float(ir_tol),
+                               int(ir_max), _vp(factors.buf), factors.buf.numel(), _vp(work), work.numel(),
+                               ctypes.byref(st) if want_stats else None, _stream(F.device))
+    L.check(code, "rad_gebhart_ref")
+    stats = st.as_dict() if want_stats else {}
+    stats["status"] = code
+    return out, factors, stats
+
+
+def ref_check(B: torch.Tensor, eps: torch.Tensor, area: torch.Tensor) -> torch.Tensor:
+    """[closure residual, reciprocity residual] of a REF matrix (eq. 4.3-4.4)."""
+    n = B.shape[0]
+    ldb = _mat(B, "B", n, n + 1)
+    _vec(eps, "eps", n)
+    _vec(area, "area", n)
+    out = torch.empty(2, dtype=torch.float64, device=B.device)
+    lib = L.lib()
+    work = WORKSPACE.get(B.device, "refcheck", lib.rad_ref_check_workspace_bytes(n))
+    code = lib.rad_ref_check(_vp(B), n, ldb, _vp(eps), _vp(area), _vp(out), _vp(work), work.numel(),
+                             _stream(B.device))
+    L.check(code, "rad_ref_check")
+    return out
+
+
+def gebhart_ref_adjoint(factors: Factors, F: torch.Tensor, rho: torch.Tensor, B: torch.Tensor,
+                        G: torch.Tensor, want_lambda: bool = False, ir_tol: float = 1e-12,
+                        ir_max: int = 4, want_stats: bool = True):
+    """Returns (grad_eps, grad_rho, Lambda or None, stats) for G = dJ/dB."""
+    n = F.shape[0]
+    ldf = _mat(F, "F", n, n + 1)
+    ldb = _mat(B, "B", n, n + 1)
+    ldg = _mat(G, "G", n, n + 1)
+    _vec(rho, "rho", n)
+    ge = torch.empty(n, dtype=torch.float64, device=F.device)
+    gr = torch.empty(n, dtype=torch.float64, device=F.device)
+    lam = torch.empty((n, n + 1), dtype=torch.float64, device=F.device) if want_lambda else None
+    ldl = lam.stride(0) if lam is not None else n + 1
+    lib = L.lib()
+    p = _PREC[factors.precision]
+    work = WORKSPACE.get(F.device, "adjoint", lib.rad_adjoint_workspace_bytes(n, p))
+    st = L.RadStats()
+    code = lib.rad_gebhart_ref_adjoint(_vp(factors.buf), factors.buf.numel(), p, _vp(F), n, ldf, _vp(rho),
+                                       _vp(B), ldb, _vp(G), ldg, _vp(ge), _vp(gr), _vp(lam), ldl,
+                                       float(ir_tol), int(ir_max), _vp(work), work.numel(),
+                                       ctypes.byref(st) if want_stats else None, _stream(F.device))
+    L.check(code, "rad_gebhart_ref_adjoint")
+    stats = st.as_dict() if want_stats else {}
+    stats["status"] = code
+    return ge, gr, lam, stats
+
+
+class GebhartREF(torch.autograd.Function):
+    """B = K(F, rho)^{-1} E(F, eps) with a hand-written adjoint backward.
+
+    forward(F, eps, rho, precision) -> B;  backward gives (None, dJ/d eps,
+    dJ/d rho, None) from the transposed solve that reuses the forward's factors.
+    F is treated as a constant.
+    """
+
+    @staticmethod
+    def forward(ctx, F, eps, rho, precision="fp64"):
+        B, factors, _ = gebhart_ref(F.detach(), eps.detach(), rho.detach(), precision=precision,
+                                    want_stats=False)
+        ctx.factors = factors
+        ctx.save_for_backward(F, rho, B)
+        return B
+
+    @staticmethod
+    def backward(ctx, G):
+        F, rho, B = ctx.saved_tensors
+        ge, gr, _, _ = gebhart_ref_adjoint(ctx.factors, F.detach(), rho.detach(), B,
+                                           G.contiguous(), want_stats=False)
+        return None, ge, gr, None

@@ -1,0 +1,97 @@
+// Internal helpers shared by the HIP translation units of librad.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/rad.h"
+
+namespace rad {
+
+// Thread-local message of the last failing call (returned by rad_last_error).
+void set_error(const std::string& msg);
+void clear_error();
+
+#define RAD_HIP_CHECK(expr)                                                      \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess) {                                                      \
+      ::rad::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));       \
+      return RAD_EHIP;                                                           \
+    }                                                                            \
+  } while (0)
+
+#define RAD_REQUIRE(cond, code, msg)                                             \
+  do {                                                                           \
+    if (!(cond)) {                                                               \
+      ::rad::set_error(msg);                                                     \
+      return (code);                                                             \
+    }                                                                            \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Simple bump allocator over a caller-provided workspace.
+struct Carve {
+  char* base;
+  size_t size;
+  size_t used = 0;
+  bool ok = true;
+  Carve(void* p, size_t n) : base(static_cast<char*>(p)), size(n) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(used, 256);
+    size_t bytes = align_up(count * sizeof(T), 256);
+    if (base == nullptr || off + bytes > size) {
+      ok = false;
+      used = off + bytes;
+      return nullptr;
+    }
+    used = off + bytes;
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// Per-launch kernel timing (see profile.hip).
+bool prof_enabled();
+hipEvent_t prof_event();
+void prof_push(int kind, hipEvent_t a, hipEvent_t b, double flops, double bytes);
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  hipStream_t s;
+  int kind;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(hipStream_t st, int k, double f, double b) : s(st), kind(k), flops(f), bytes(b) {
+    if (prof_enabled()) {
+      a = prof_event();
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = prof_event();
+      if (b) hipEventRecord(b, s);
+      prof_push(kind, a, b, flops, bytes);
+    }
+  }
+};
+
+// Device status codes raised by kernels (stored in an int32 flag; the
+// smallest (most negative) code wins via atomicMin).
+__device__ inline void raise_status(int* flag, int code) { atomicMin(flag, code); }
+
+// Non-negative doubles order like their bit patterns: atomicMax on the
+// bits gives an order-independent, reproducible max.
+__device__ inline void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p),
+            static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+}  // namespace rad

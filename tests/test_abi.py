@@ -1,0 +1,44 @@
+"""CPU checks of the C ABI: the library loads and exports what include/rad.h declares."""
+import pathlib
+import re
+
+from paper_2511_04277_amd import _lib
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+def declared_symbols():
+    text = (ROOT / "include" / "rad.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rad_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    decl = declared_symbols()
+    assert decl, "no declarations found"
+    assert sorted(_lib.SIGNATURES) == decl
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.lib()
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_status_strings_and_workspace_queries():
+    lib = _lib.lib()
+    assert lib.rad_status_string(-4).decode() == "singular pivot block"
+    assert lib.rad_enforce_workspace_bytes(0) == 0
+    assert lib.rad_enforce_workspace_bytes(1000) > 8 * 1000
+    assert lib.rad_aggregate_workspace_bytes(1000, 10) >= 4 * 1000
+
+
+def test_host_side_argument_errors_need_no_gpu():
+    # argument validation happens before any device call
+    lib = _lib.lib()
+    code = lib.rad_enforce_vf(None, 10, 11, None, None, 0, 0.0, 1, None, 0, None, None)
+    assert code == _lib.RAD_EINVAL
+    assert b"NULL" in lib.rad_last_error()
+    code = lib.rad_enforce_vf(_lib.ctypes.c_void_p(256), 10, 5, _lib.ctypes.c_void_p(256), None, 1, 0.0, 1,
+                              None, 0, None, None)
+    assert code == _lib.RAD_EINVAL and b"ldf" in lib.rad_last_error()
