@@ -24,6 +24,8 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("RAD_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # keep MFMA accumulators in VGPRs (no per-iteration AGPR copies)
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-result", "-I", str(ROOT / "include")]
 
 

@@ -5,13 +5,14 @@
 //   sweep    : each workgroup owns a tile pair {(I,J), (J,I)}, I <= J, of the
 //              square block (64 x 64 doubles each).  On load it applies the
 //              closure scale of the previous iteration (F_ij / s_i, eq. 3.39-
-//              3.40 with omega = eta), then the reciprocity step (eq. 3.18-
-//              3.20, kappa from eq. 3.25 or 1/2) using an LDS transpose so
-//              both tiles are read and written with coalesced rows; it emits
-//              per-(row, column-tile) partial row sums of the new values.
-//              Diagonal-tile workgroups also carry the space column.
+//              3.40 with omega = eta, as a product with 1/s_i), then the
+//              reciprocity step (eq. 3.18-3.20, kappa from eq. 3.25 or 1/2),
+//              reading the partner tile through LDS so both tiles are read and
+//              written as coalesced rows; it emits per-(row, column-tile)
+//              partial row sums of the new values.  Diagonal-tile workgroups
+//              also carry the space column.
 //   finalize : s_i = sum of the partials in fixed tile order (reproducible),
-//              closure defect max |s_i - 1|.
+//              stores 1/s_i, closure defect max |s_i - 1|.
 //   decide   : convergence flag and statistics (device-side, no host sync).
 // The last closure scale is applied by a final streaming pass.
 #include "common.h"
@@ -60,123 +61,163 @@ __device__ inline void pair_from_index(long p, int t, int& I, int& J) {
   J = static_cast<int>(i + (p - start(i)));
 }
 
+// Thread t owns row r = t / 4 of the 64 x 64 tile (I, J) and its 16
+// consecutive columns cq*16 .. cq*16+15 (cq = t % 4) in registers; the partner
+// tile (J, I) sits in LDS.  Both tiles are read and written as 128-byte runs.
 __global__ void __launch_bounds__(ENF_THREADS)
 enf_sweep(double* __restrict__ F, long ldf, int n, int t,
-          const double* __restrict__ area, const double* __restrict__ nrays,
-          int mode, const double* __restrict__ scale, double* __restrict__ partial,
-          EnfCtrl* ctrl, int parity, int first) {
+          const double* __restrict__ area, const double* __restrict__ inv_area,
+          const double* __restrict__ nrays, int mode, const double* __restrict__ inv_scale,
+          double* __restrict__ partial, double* __restrict__ blkmax, EnfCtrl* ctrl, int first) {
   if (ctrl->converged || ctrl->status < 0) return;
-  __shared__ double sA[ET][ETP];
   __shared__ double sB[ET][ETP];
-  __shared__ double red[3][ENF_THREADS / 64];
+  __shared__ double red[2][ENF_THREADS / 64];
   int I, J;
   pair_from_index(blockIdx.x, t, I, J);
   const int r0 = I * ET, c0 = J * ET;
   const int tid = threadIdx.x;
-  const int c = tid & (ET - 1);
-  const int rg = tid >> 6;   // 0..3
+  const int r = tid >> 2, cq = tid & 3, cb = cq * 16;
   const bool diag = (I == J);
+  const int i = r0 + r;          // this thread's row of tile (I, J)
+  const int ip = c0 + r;         // this thread's row of the partner tile (J, I)
   int bad = 0;
 
-  // load tile A = F[r0.., c0..] and B = F[c0.., r0..] (scaled) into LDS
-  for (int m = 0; m < ET / 4; ++m) {
-    int r = rg + 4 * m;
-    int i = r0 + r, j = c0 + c;
-    double v = 0.0;
-    if (i < n && j < n) {
-      v = F[static_cast<long>(i) * ldf + j];
-      bad |= !(v >= 0.0) || !(v <= 1.0e300);
-      if (!first) v = v / scale[i];
-    }
-    sA[r][c] = v;
-    if (!diag) {
-      int i2 = c0 + r, j2 = r0 + c;
-      double w = 0.0;
-      if (i2 < n && j2 < n) {
-        w = F[static_cast<long>(i2) * ldf + j2];
-        bad |= !(w >= 0.0) || !(w <= 1.0e300);
-        if (!first) w = w / scale[i2];
-      }
-      sB[r][c] = w;
-    }
-  }
-  __syncthreads();
-
-  // reciprocity on the pair; each unordered pair {i,j}, i != j, once
-  double rmax = 0.0, emax = 0.0;
-  for (int m = 0; m < ET / 4; ++m) {
-    int r = rg + 4 * m;
-    int i = r0 + r, j = c0 + c;
-    if (i >= n || j >= n) continue;
-    if (diag) {
-      if (c <= r) continue;  // handled by the (c, r) thread; diagonal unchanged
-      double fij = sA[r][c], fji = sA[c][r];
-      double ai = area[i], aj = area[j];
-      double eij = ai * fij, eji = aj * fji;
-      rmax = fmax(rmax, fabs(eij - eji));
-      emax = fmax(emax, fmax(eij, eji));
-      double ni = nrays ? nrays[i] : 1.0, nj = nrays ? nrays[j] : 1.0;
-      double k = kappa_of(fij, fji, ai, aj, ni, nj, mode);
-      double eh = k * eij + (1.0 - k) * eji;
-      sA[r][c] = eh / ai;
-      sA[c][r] = eh / aj;
+  // Interior tiles (the vast majority) load and store unconditionally; edge
+  // tiles clamp their addresses and zero the entries beyond n, which the pair
+  // arithmetic below leaves at zero.
+  const bool interior = (r0 + ET <= n) && (c0 + ET <= n);
+  double a[16];
+  {
+    const int ic = i < n ? i : n - 1;
+    const double si = first ? 1.0 : inv_scale[ic];
+    const double* src = F + static_cast<long>(ic) * ldf;
+    if (interior) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) a[e] = src[c0 + cb + e];
     } else {
-      double fij = sA[r][c], fji = sB[c][r];
-      double ai = area[i], aj = area[j];
-      double eij = ai * fij, eji = aj * fji;
-      rmax = fmax(rmax, fabs(eij - eji));
-      emax = fmax(emax, fmax(eij, eji));
-      double ni = nrays ? nrays[i] : 1.0, nj = nrays ? nrays[j] : 1.0;
-      double k = kappa_of(fij, fji, ai, aj, ni, nj, mode);
-      double eh = k * eij + (1.0 - k) * eji;
-      sA[r][c] = eh / ai;
-      sB[c][r] = eh / aj;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int j = c0 + cb + e;
+        const double v = src[j < n ? j : n - 1];
+        a[e] = (i < n && j < n) ? v : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      bad |= !(a[e] >= 0.0) || !(a[e] <= 1.0e300);
+      a[e] *= si;
     }
   }
-  if (diag) {
-    // diagonal entries keep their (scaled) value; include them in eta max
-    if (tid < ET && r0 + tid < n) emax = fmax(emax, area[r0 + tid] * sA[tid][tid]);
+  if (!diag) {
+    const int ipc = ip < n ? ip : n - 1;
+    const double sj = first ? 1.0 : inv_scale[ipc];
+    const double* src = F + static_cast<long>(ipc) * ldf;
+    double v[16];
+    if (interior) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = src[r0 + cb + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int j = r0 + cb + e;
+        const double x = src[j < n ? j : n - 1];
+        v[e] = (ip < n && j < n) ? x : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      bad |= !(v[e] >= 0.0) || !(v[e] <= 1.0e300);
+      sB[r][cb + e] = v[e] * sj;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sB[r][cb + e] = a[e];
   }
   __syncthreads();
 
-  // write both tiles back (coalesced rows)
-  for (int m = 0; m < ET / 4; ++m) {
-    int r = rg + 4 * m;
-    int i = r0 + r, j = c0 + c;
-    if (i < n && j < n) F[static_cast<long>(i) * ldf + j] = sA[r][c];
-    if (!diag) {
-      int i2 = c0 + r, j2 = r0 + c;
-      if (i2 < n && j2 < n) F[static_cast<long>(i2) * ldf + j2] = sB[r][c];
+  // reciprocity on each unordered pair {i, j}, i != j, exactly once
+  double rmax = 0.0, emax = 0.0;
+  const int ic = i < n ? i : n - 1;
+  const double ai = area[ic];
+  const double iai = inv_area[ic];
+  const double ni = nrays ? nrays[ic] : 1.0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int c = cb + e;
+    const int j = c0 + c;
+    const int jc = j < n ? j : n - 1;
+    if (diag) {
+      if (c == r) emax = fmax(emax, ai * a[e]);  // diagonal keeps its value
+      if (c <= r) continue;                       // handled by the owner of (c, r)
+    }
+    const double fij = a[e], fji = sB[c][r];
+    const double aj = area[jc];
+    const double eij = ai * fij, eji = aj * fji;
+    rmax = fmax(rmax, fabs(eij - eji));
+    emax = fmax(emax, fmax(eij, eji));
+    const double nj = nrays ? nrays[jc] : 1.0;
+    const double k = kappa_of(fij, fji, ai, aj, ni, nj, mode);
+    const double eh = k * eij + (1.0 - k) * eji;
+    a[e] = eh * iai;
+    sB[c][r] = eh * inv_area[jc];
+  }
+  __syncthreads();
+  if (diag) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if (cb + e < r) a[e] = sB[r][cb + e];  // lower-triangle values written by their pair owner
+  }
+
+  // write back and form the partial row sums (4-lane reductions, fixed order)
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) sa += a[e];
+  if (interior) {
+    double* dst = F + static_cast<long>(i) * ldf + c0 + cb;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[e] = a[e];
+  } else if (i < n) {
+    double* dst = F + static_cast<long>(i) * ldf + c0 + cb;
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if (c0 + cb + e < n) dst[e] = a[e];
+  }
+  if (!diag) {
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      v[e] = sB[r][cb + e];
+      sb += v[e];
+    }
+    double* dst = F + static_cast<long>(ip) * ldf + r0 + cb;
+    if (interior) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) dst[e] = v[e];
+    } else if (ip < n) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (r0 + cb + e < n) dst[e] = v[e];
     }
   }
-  // partial row sums in a fixed order: thread r < 64 sums row r of sA,
-  // threads 64..127 sum the rows of sB; diagonal tiles add the space column.
-  if (tid < ET) {
-    int i = r0 + tid;
+  sa += __shfl_xor(sa, 1);
+  sa += __shfl_xor(sa, 2);
+  sb += __shfl_xor(sb, 1);
+  sb += __shfl_xor(sb, 2);
+  if (cq == 0) {
     if (i < n) {
-      double s = 0.0;
-      for (int q = 0; q < ET; ++q) s += sA[tid][q];
-      if (diag) {
+      partial[static_cast<long>(J) * n + i] = sa;
+      if (diag) {  // the space column of row i rides with the diagonal tile
         double* sp = F + static_cast<long>(i) * ldf + n;
         double v = *sp;
         bad |= !(v >= 0.0) || !(v <= 1.0e300);
-        if (!first) v = v / scale[i];
+        if (!first) v *= inv_scale[i];
         *sp = v;
         partial[static_cast<long>(t) * n + i] = v;
       }
-      partial[static_cast<long>(J) * n + i] = s;
     }
-  } else if (tid < 2 * ET && !diag) {
-    int rr = tid - ET;
-    int i = c0 + rr;
-    if (i < n) {
-      double s = 0.0;
-      for (int q = 0; q < ET; ++q) s += sB[rr][q];
-      partial[static_cast<long>(I) * n + i] = s;
-    }
+    if (!diag && ip < n) partial[static_cast<long>(I) * n + ip] = sb;
   }
   if (bad) raise_status(&ctrl->status, RAD_ENONFINITE);
-  // block max of the reciprocity error and of eta
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_xor(rmax, off));
     emax = fmax(emax, __shfl_xor(emax, off));
@@ -187,31 +228,44 @@ enf_sweep(double* __restrict__ F, long ldf, int n, int t,
   }
   __syncthreads();
   if (tid == 0) {
-    double a = red[0][0], b = red[1][0];
+    double x = red[0][0], y = red[1][0];
     for (int w = 1; w < ENF_THREADS / 64; ++w) {
-      a = fmax(a, red[0][w]);
-      b = fmax(b, red[1][w]);
+      x = fmax(x, red[0][w]);
+      y = fmax(y, red[1][w]);
     }
-    atomic_max_nonneg(&ctrl->recip[parity], a);
-    atomic_max_nonneg(&ctrl->etamax[parity], b);
+    blkmax[2 * static_cast<long>(blockIdx.x)] = x;
+    blkmax[2 * static_cast<long>(blockIdx.x) + 1] = y;
   }
 }
 
 __global__ void __launch_bounds__(256)
-enf_finalize(int n, int t, const double* __restrict__ partial, double* __restrict__ scale,
-             EnfCtrl* ctrl, int parity) {
+enf_finalize(int n, int t, const double* __restrict__ partial, double* __restrict__ scale /* 1/s */,
+             const double* __restrict__ blkmax, long nblk, EnfCtrl* ctrl, int parity) {
   if (ctrl->converged || ctrl->status < 0) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double d = 0.0;
   if (i < n) {
     double s = 0.0;
     for (int q = 0; q <= t; ++q) s += partial[static_cast<long>(q) * n + i];
     if (!(s > 0.0)) raise_status(&ctrl->status, RAD_EZEROROW);
-    scale[i] = s;
+    scale[i] = 1.0 / s;
     d = fabs(s - 1.0);
   }
-  for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&ctrl->defect[parity], d);
+  double rm = 0.0, em = 0.0;
+  for (long b = i; b < nblk; b += static_cast<long>(gridDim.x) * blockDim.x) {
+    rm = fmax(rm, blkmax[2 * b]);
+    em = fmax(em, blkmax[2 * b + 1]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    d = fmax(d, __shfl_xor(d, off));
+    rm = fmax(rm, __shfl_xor(rm, off));
+    em = fmax(em, __shfl_xor(em, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(&ctrl->defect[parity], d);
+    atomic_max_nonneg(&ctrl->recip[parity], rm);
+    atomic_max_nonneg(&ctrl->etamax[parity], em);
+  }
 }
 
 __global__ void enf_decide(EnfCtrl* ctrl, int parity, double tol) {
@@ -234,9 +288,18 @@ enf_apply_scale(double* __restrict__ F, long ldf, int n, const double* __restric
                 const EnfCtrl* ctrl) {
   if (ctrl->status < 0 || ctrl->iters == 0) return;
   const long row = blockIdx.x;
-  const double s = scale[row];
+  const double s = scale[row];  // 1 / row sum
   double* p = F + row * ldf;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) p[j] = p[j] / s;
+  for (int j = threadIdx.x; j <= n; j += blockDim.x) p[j] = p[j] * s;
+}
+
+__global__ void __launch_bounds__(256)
+enf_inv_area(const double* __restrict__ area, int n, double* __restrict__ inv_area, EnfCtrl* ctrl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = area[i];
+  if (!(a > 0.0 && a <= 1.0e300)) raise_status(&ctrl->status, RAD_EINVAL);
+  inv_area[i] = 1.0 / a;
 }
 
 __global__ void enf_init(EnfCtrl* ctrl) {
@@ -253,6 +316,8 @@ __global__ void enf_init(EnfCtrl* ctrl) {
 struct EnfLayout {
   EnfCtrl* ctrl;
   double* scale;
+  double* inv_area;
+  double* blkmax;
   double* partial;
   size_t bytes;
   bool ok;
@@ -264,6 +329,8 @@ EnfLayout enf_layout(void* work, size_t work_bytes, int64_t n) {
   EnfLayout l;
   l.ctrl = cv.take<EnfCtrl>(1);
   l.scale = cv.take<double>(static_cast<size_t>(n));
+  l.inv_area = cv.take<double>(static_cast<size_t>(n));
+  l.blkmax = cv.take<double>(static_cast<size_t>(t * (t + 1)));
   l.partial = cv.take<double>(static_cast<size_t>((t + 1) * n));
   l.bytes = cv.used;
   l.ok = cv.ok;
@@ -302,6 +369,8 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
   const long pairs = static_cast<long>(t) * (t + 1) / 2;
   RAD_REQUIRE(pairs < (1L << 31), RAD_EINVAL, "rad_enforce_vf: too many tiles");
   hipLaunchKernelGGL(enf_init, dim3(1), dim3(64), 0, s, l.ctrl);
+  hipLaunchKernelGGL(enf_inv_area, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, area,
+                     static_cast<int>(n), l.inv_area, l.ctrl);
   // tol mode: launch iterations in batches; a converged flag makes the rest
   // of a batch exit at once, so the stop is exact without a sync per step.
   const int batch = tol > 0.0 ? 8 : max_iter;
@@ -314,11 +383,11 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
       {
         ProfScope prof(s, RAD_PROF_ENFORCE_SWEEP, 0.0, 16.0 * static_cast<double>(n) * (n + 1));
         hipLaunchKernelGGL(enf_sweep, dim3(static_cast<unsigned>(pairs)), dim3(ENF_THREADS), 0, s,
-                           F, static_cast<long>(ldf), static_cast<int>(n), t, area, n_rays,
-                           kappa_mode, l.scale, l.partial, l.ctrl, parity, it == 0 ? 1 : 0);
+                           F, static_cast<long>(ldf), static_cast<int>(n), t, area, l.inv_area, n_rays,
+                           kappa_mode, l.scale, l.partial, l.blkmax, l.ctrl, it == 0 ? 1 : 0);
       }
       hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s,
-                         static_cast<int>(n), t, l.partial, l.scale, l.ctrl, parity);
+                         static_cast<int>(n), t, l.partial, l.scale, l.blkmax, pairs, l.ctrl, parity);
       hipLaunchKernelGGL(enf_decide, dim3(1), dim3(64), 0, s, l.ctrl, parity, tol);
     }
     RAD_HIP_CHECK(hipGetLastError());

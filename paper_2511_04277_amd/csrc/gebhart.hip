@@ -6,24 +6,32 @@
 // K is strictly diagonally dominant by rows (sum_k rho_k F_ik <= max rho < 1),
 // so block Gaussian elimination needs no pivoting and every Schur complement
 // stays dominant.  The factorization is a block LDU with 128 x 128 blocks that
-// never splits a diagonal block:  for panel k,
-//   D_k^{-1}       Gauss-Jordan inverse of the diagonal block (one workgroup, LDS)
-//   X   = A21 D^{-1}                (MFMA GEMM, in place: block column of L)
-//   A22 -= X A12,  Y2 -= X Y1       (MFMA GEMM over the trailing matrix and the
-//                                     n+1 right-hand sides in one launch)
+// never splits a diagonal block:  for block k,
+//   D_k^{-1}        Gauss-Jordan inverse of the diagonal block (one workgroup)
+//   X  = A21 D^{-1} (block column of L, in place)
+//   A22 -= X A12,   Y2 -= X Y1    (trailing matrix and the n+1 right-hand sides)
 // so K = L U with L block-unit-lower (blocks X) and U block-upper (diagonal
-// blocks D_k, off-diagonal blocks A12); the forward substitution of E is
-// fused into the trailing updates.  Back substitution: B_k = D_k^{-1} Y_k,
-// Y_top -= U_top,k B_k.  The matrix K is padded to a multiple of 128 with
-// identity blocks, which leaves the solution unchanged.
+// blocks D_k, off-diagonal blocks A12); the forward substitution of E rides
+// along with the elimination.  The updates are organised in two levels: inside
+// a 1024-wide panel the 128-wide blocks update only the panel (and the panel's
+// own rows to its right), and the rest of the matrix receives one K = 1024 MFMA
+// GEMM per panel, which keeps the FP64/FP32 matrix cores busy instead of
+// streaming the trailing matrix once per 128 columns.  Back substitution and
+// the transposed (adjoint) solves use the same two-level order.
 //
-// RAD_PREC_FP32_IR runs the same factorization and solves in FP32 MFMA, then
-// refines in FP64: R = E - K B = (E - B) + F_sq diag(rho) B as an FP64 MFMA
-// GEMM, delta = K^{-1} R with the FP32 factors, B += delta.
+// All GEMM operands are the solver's own buffers, padded to multiples of 128
+// rows / columns (K with identity blocks, right-hand sides and the refinement
+// operands with zeros), so the MFMA kernel reads unpredicated tiles and only
+// masks its stores; results are copied to the caller's arrays at the end.
+//
+// RAD_PREC_FP32_IR runs the factorization and solves in FP32 MFMA, then
+// refines in FP64:  R = E - K X = (E - X) + P X with P = F_sq diag(rho) (FP64
+// MFMA GEMM), delta = K^{-1} R with the FP32 factors, X += delta.
 //
 // Adjoint: K^T = U^T L^T, so Lambda = K^{-T} G is a block forward solve with
 // U^T (diagonal blocks D_k^{-T}) followed by a block backward solve with L^T,
-// both reusing the stored factors through transposed-A GEMMs.
+// both reusing the stored factors through transposed-A GEMMs; in FP32_IR mode
+// the residual G - K^T Lambda = (G - Lambda) + P^T Lambda is formed in FP64.
 #include "common.h"
 #include "gemm.h"
 
@@ -33,8 +41,8 @@
 namespace rad {
 namespace {
 
-constexpr int NB = 128;          // factorization block
-constexpr int GJ_THREADS = 1024;
+constexpr int NB = 128;          // diagonal block (Gauss-Jordan inverse)
+constexpr int NB2 = 1024;        // panel width of the two-level updates
 
 template <class T>
 constexpr long pad_elems() { return 128 / static_cast<long>(sizeof(T)); }
@@ -59,14 +67,15 @@ FactorLayout factor_layout(int64_t n) {
   return f;
 }
 
-inline long rhs_ld(int64_t n, long pad) { return static_cast<long>(ceil_div(n + 1, 64) * 64 + pad); }
+// right-hand-side buffers: columns padded to a multiple of 128 plus 128 bytes
+inline long rhs_ld(int64_t n, long pad) { return static_cast<long>(ceil_div(n + 1, 128) * 128 + pad); }
 
 struct Scalars {
   int status;
   int pad;
   double max_r;      // max |residual|
   double max_d;      // max |correction|
-  double red[2];     // REF check outputs / spare
+  double red[2];     // REF check outputs
 };
 
 template <class T>
@@ -106,15 +115,6 @@ __global__ void scalars_init_partial(Scalars* sc) {
   }
 }
 
-// R = G - Lambda (fp64)
-__global__ void __launch_bounds__(256)
-adj_residual_init(const double* __restrict__ G, long ldg, int n, const double* __restrict__ L, long ldl,
-                  double* __restrict__ R, long ldr) {
-  const int i = blockIdx.x;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    R[static_cast<long>(i) * ldr + j] = G[static_cast<long>(i) * ldg + j] - L[static_cast<long>(i) * ldl + j];
-}
-
 __global__ void check_optical(const double* __restrict__ eps, const double* __restrict__ rho,
                               int n, Scalars* sc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,18 +124,19 @@ __global__ void check_optical(const double* __restrict__ eps, const double* __re
 }
 
 // K (padded with identity) and E (padded with zeros) in precision T.
+// Row i of both, one workgroup per row of the padded size.
 template <class T>
 __global__ void __launch_bounds__(256)
 geb_form(const double* __restrict__ F, long ldf, int n, const double* __restrict__ eps,
          const double* __restrict__ rho, T* __restrict__ KF, long ldk, int np,
-         T* __restrict__ Y, long ldy, int wy, Scalars* sc) {
+         T* __restrict__ Y, long ldy, Scalars* sc) {
   const int i = blockIdx.x;
   const double* frow = F + static_cast<long>(i) * ldf;
   T* krow = KF + static_cast<long>(i) * ldk;
   T* yrow = Y + static_cast<long>(i) * ldy;
   int bad = 0;
-  const int jend = np > wy ? np : wy;
-  for (int j = threadIdx.x; j < jend; j += blockDim.x) {
+  const long jend = ldk > ldy ? ldk : ldy;
+  for (long j = threadIdx.x; j < jend; j += blockDim.x) {
     double kv = (i == j) ? 1.0 : 0.0;
     double yv = 0.0;
     if (i < n && j <= n) {
@@ -148,71 +149,112 @@ geb_form(const double* __restrict__ F, long ldf, int n, const double* __restrict
         yv = f;  // space column: no emissivity factor (eq. B.6)
       }
     }
-    if (j < np) krow[j] = static_cast<T>(kv);
-    if (j < wy) yrow[j] = static_cast<T>(yv);
+    if (j < ldk) krow[j] = (j < np) ? static_cast<T>(kv) : T(0);
+    if (j < ldy) yrow[j] = static_cast<T>(yv);
   }
   if (bad) raise_status(&sc->status, RAD_ENONFINITE);
 }
 
-// In-place Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting.
+// P = F_sq diag(rho) in FP64, zero outside n x n (refinement residuals).
+__global__ void __launch_bounds__(256)
+form_p64(const double* __restrict__ F, long ldf, int n, const double* __restrict__ rho,
+         double* __restrict__ P, long ldp) {
+  const int i = blockIdx.x;
+  for (long j = threadIdx.x; j < ldp; j += blockDim.x)
+    P[static_cast<long>(i) * ldp + j] = (i < n && j < n) ? F[static_cast<long>(i) * ldf + j] * rho[j] : 0.0;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) {
+  for (long q = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; q < count;
+       q += static_cast<long>(gridDim.x) * blockDim.x)
+    p[q] = T(0);
+}
+
+// Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting.  Thread t
+// keeps column j = t % NB of the 16 contiguous rows g*16 .. g*16+15
+// (g = t / NB) in registers.  Step p is one uniform update
+//   m_ij <- m_ij - c_i r_j,   r_j = m_pj d (j != p), r_p = d = 1 / m_pp,
+//                             c_i = m_ip (i != p),   c_p = -1,
+// after row p and column p have been published through LDS and zeroed in
+// registers: that yields the new row p (r), column p (-c d) and pivot (d) of
+// the in-place inverse with one FMA per element.  Pivots are taken in the
+// order p = g*16 + q (q outer), which keeps register indices static; any
+// order of diagonal pivots gives the same inverse and diagonal dominance
+// makes every order stable.  LDS is double-buffered, one barrier per step.
+constexpr int GJ_THREADS = 1024;
+
+// 1/x: hardware reciprocal refined by Newton steps to full precision
+__device__ __forceinline__ double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+__device__ __forceinline__ float recip_nr(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+}
+
 template <class T>
 __global__ void __launch_bounds__(GJ_THREADS)
 gj_inverse(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
-  __shared__ T M[NB][NB + 1];
+  constexpr int G = GJ_THREADS / NB;  // 8 row groups
+  constexpr int R = NB / G;           // 16 rows per thread
+  __shared__ T sRow[2][NB];
+  __shared__ __attribute__((aligned(16))) T sCol[2][NB];
   const int tid = threadIdx.x;
   const int j = tid & (NB - 1);
-  const int i0 = tid >> 7;                 // 0..7
-  constexpr int R = NB / (GJ_THREADS / NB); // 16 rows per thread
-  for (int q = 0; q < R; ++q) {
-    int i = i0 + 8 * q;
-    M[i][j] = A[static_cast<long>(i) * lda + j];
-  }
-  __syncthreads();
+  const int g = tid / NB;
+  T m[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) m[q] = A[static_cast<long>(g * R + q) * lda + j];
+  const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
   int singular = 0;
-  for (int p = 0; p < NB; ++p) {
-    T piv = M[p][p];
-    T mpj = M[p][j];
-    T mip[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) mip[q] = M[i0 + 8 * q][p];
-    __syncthreads();
-    T d = T(1) / piv;
-    // K has unit diagonal scale and its pivots stay >= 1 - max rho for valid
-    // input; a pivot below this threshold means a (numerically) singular K.
-    const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
-    if (!(fabs(static_cast<double>(piv)) > tiny) || !(fabs(static_cast<double>(d)) < 1e300)) {
-      singular = 1;
-      d = T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      int i = i0 + 8 * q;
-      T v;
-      if (i == p) {
-        v = (j == p) ? d : mpj * d;
-      } else if (j == p) {
-        v = -mip[q] * d;
-      } else {
-        v = M[i][j] - mip[q] * (mpj * d);
+  for (int q0 = 0; q0 < R; ++q0) {
+#pragma unroll 1
+    for (int gg = 0; gg < G; ++gg) {
+      const int p = gg * R + q0;
+      const int buf = gg & 1;  // alternates every step (G is even)
+      if (g == gg) {  // owner of row p publishes it and clears it
+        sRow[buf][j] = m[q0];
+        m[q0] = T(0);
       }
-      M[i][j] = v;
+      if (j == p) {   // owner of column p publishes it (c_p = -1) and clears it
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          sCol[buf][g * R + q] = (g == gg && q == q0) ? T(-1) : m[q];
+          m[q] = T(0);
+        }
+      }
+      __syncthreads();
+      const T piv = sRow[buf][p];
+      T d = recip_nr(piv);
+      // K has unit diagonal scale and its pivots stay >= 1 - max rho for
+      // valid input; a pivot below this threshold means a singular K.
+      if (!(fabs(static_cast<double>(piv)) > tiny) || !(fabs(static_cast<double>(d)) < 1e300)) {
+        singular = 1;
+        d = T(0);
+      }
+      const T rj = (j == p) ? d : sRow[buf][j] * d;
+      const T* col = &sCol[buf][g * R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) m[q] = m[q] - col[q] * rj;
     }
-    __syncthreads();
   }
-  for (int q = 0; q < R; ++q) {
-    int i = i0 + 8 * q;
-    out[i * NB + j] = M[i][j];
-  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) out[(g * R + q) * NB + j] = m[q];
   if (singular && tid == 0) raise_status(&sc->status, RAD_ESINGULAR);
 }
 
-// B (fp64, n x (n+1)) <- Y (T)
-template <class T>
+// dst (D, rows < n, cols <= n) <- src (S)
+template <class S, class D>
 __global__ void __launch_bounds__(256)
-store_solution(const T* __restrict__ Y, long ldy, int n, double* __restrict__ B, long ldb) {
+copy_block(const S* __restrict__ src, long lds, int n, D* __restrict__ dst, long ldd) {
   const int i = blockIdx.x;
   for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    B[static_cast<long>(i) * ldb + j] = static_cast<double>(Y[static_cast<long>(i) * ldy + j]);
+    dst[static_cast<long>(i) * ldd + j] = static_cast<D>(src[static_cast<long>(i) * lds + j]);
 }
 
 __device__ inline void block_max(double v, double* target) {
@@ -220,21 +262,28 @@ __device__ inline void block_max(double v, double* target) {
   if ((threadIdx.x & 63) == 0) atomic_max_nonneg(target, v);
 }
 
-// R = E - B  (fp64), E from F and eps on the fly
+// R = E - X  (rows < n, cols <= n), E from F and eps on the fly
 __global__ void __launch_bounds__(256)
 residual_init(const double* __restrict__ F, long ldf, int n, const double* __restrict__ eps,
-              const double* __restrict__ B, long ldb, double* __restrict__ R, long ldr) {
+              const double* __restrict__ X, long ldx, double* __restrict__ R, long ldr) {
   const int i = blockIdx.x;
   const double* f = F + static_cast<long>(i) * ldf;
-  const double* b = B + static_cast<long>(i) * ldb;
-  double* r = R + static_cast<long>(i) * ldr;
   for (int j = threadIdx.x; j <= n; j += blockDim.x) {
     double e = (j < n) ? f[j] * eps[j] : f[n];
-    r[j] = e - b[j];
+    R[static_cast<long>(i) * ldr + j] = e - X[static_cast<long>(i) * ldx + j];
   }
 }
 
-// Y32 <- R (rows < n), records max |R|
+// R = G - L  (rows < n, cols <= n)
+__global__ void __launch_bounds__(256)
+adj_residual_init(const double* __restrict__ G, long ldg, int n, const double* __restrict__ L, long ldl,
+                  double* __restrict__ R, long ldr) {
+  const int i = blockIdx.x;
+  for (int j = threadIdx.x; j <= n; j += blockDim.x)
+    R[static_cast<long>(i) * ldr + j] = G[static_cast<long>(i) * ldg + j] - L[static_cast<long>(i) * ldl + j];
+}
+
+// Y32 <- R (rows < n, cols <= n), records max |R|
 __global__ void __launch_bounds__(256)
 residual_to_rhs(const double* __restrict__ R, long ldr, int n, float* __restrict__ Y, long ldy,
                 Scalars* sc) {
@@ -248,7 +297,7 @@ residual_to_rhs(const double* __restrict__ R, long ldr, int n, float* __restrict
   block_max(m, &sc->max_r);
 }
 
-// X += Y32 (rows < n), records max |delta|
+// X += Y32 (rows < n, cols <= n), records max |delta|
 __global__ void __launch_bounds__(256)
 apply_correction(const float* __restrict__ Y, long ldy, int n, double* __restrict__ X, long ldx,
                  Scalars* sc) {
@@ -262,13 +311,13 @@ apply_correction(const float* __restrict__ Y, long ldy, int n, double* __restric
   block_max(m, &sc->max_d);
 }
 
-// Y (T, padded rows zero) <- G (fp64)
+// Y (T, np rows x ldy, zero outside n x (n+1)) <- G (fp64)
 template <class T>
 __global__ void __launch_bounds__(256)
-load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long ldy, int wy) {
+load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long ldy) {
   const int i = blockIdx.x;
   T* y = Y + static_cast<long>(i) * ldy;
-  for (int j = threadIdx.x; j < wy; j += blockDim.x)
+  for (long j = threadIdx.x; j < ldy; j += blockDim.x)
     y[j] = (j <= n && i < n) ? static_cast<T>(G[static_cast<long>(i) * ldg + j]) : T(0);
 }
 
@@ -318,14 +367,27 @@ __global__ void copy_scalars_out(const Scalars* sc, double* out) {
   }
 }
 
-// grad_eps[k] = sum_i Lambda_ik F_ik   (column reduction, fixed order)
+// grad_eps[k] = sum_i Lambda_ik F_ik: partial sums over row chunks of 128,
+// then a fixed-order sum of the partials (reproducible).
+constexpr int GE_ROWS = 128;
 __global__ void __launch_bounds__(256)
-adj_grad_eps(const double* __restrict__ L, long ldl, const double* __restrict__ F, long ldf,
-             int n, double* __restrict__ ge) {
+adj_grad_eps_partial(const double* __restrict__ L, long ldl, const double* __restrict__ F, long ldf,
+                     int n, double* __restrict__ part) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k >= n) return;
+  const int i0 = c * GE_ROWS, i1 = min(n, i0 + GE_ROWS);
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) s += L[static_cast<long>(i) * ldl + k] * F[static_cast<long>(i) * ldf + k];
+  part[static_cast<long>(c) * n + k] = s;
+}
+
+__global__ void __launch_bounds__(256)
+adj_grad_eps_final(const double* __restrict__ part, int n, int chunks, double* __restrict__ ge) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += L[static_cast<long>(i) * ldl + k] * F[static_cast<long>(i) * ldf + k];
+  for (int c = 0; c < chunks; ++c) s += part[static_cast<long>(c) * n + k];
   ge[k] = s;
 }
 
@@ -365,15 +427,6 @@ adj_grad_rho_direct(const double* __restrict__ L, long ldl, const double* __rest
   if (threadIdx.x == 0) gr[k] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Lambda_out (fp64, n x (n+1)) <- Y (T)
-template <class T>
-__global__ void __launch_bounds__(256)
-copy_out(const T* __restrict__ Y, long ldy, int n, double* __restrict__ X, long ldx) {
-  const int i = blockIdx.x;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    X[static_cast<long>(i) * ldx + j] = static_cast<double>(Y[static_cast<long>(i) * ldy + j]);
-}
-
 // ---------------------------------------------------------------- drivers ---
 #define RAD_GEMM(args, trans)                                  \
   do {                                                         \
@@ -381,83 +434,147 @@ copy_out(const T* __restrict__ Y, long ldy, int n, double* __restrict__ X, long 
     if (_e != hipSuccess) return _e;                           \
   } while (0)
 
-// LDU factorization of K in place; if Y is given, its rows are eliminated too.
+// Y[r_dst..) -= op(A) * Y[r_src..] (+ optional second segment), small helper
+template <class T>
+inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
+  return gemm_args<T>(A, lda, M, K, T(-1), T(1));
+}
+
+// LDU factorization of K in place; Y (if given, n+1 columns) is eliminated too.
 template <class T>
 hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc, hipStream_t s) {
-  for (int k = 0; k < f.P; ++k) {
-    const long r0 = static_cast<long>(k) * NB;
-    T* akk = f.kf + r0 * f.ldk + r0;
-    T* dk = f.dinv + r0 * NB;
-    {
-      ProfScope prof(s, RAD_PROF_DIAG_INVERSE, 2.0 * NB * NB * NB, 0.0);
-      hipLaunchKernelGGL(gj_inverse<T>, dim3(1), dim3(GJ_THREADS), 0, s, akk, f.ldk, dk, sc);
+  const long ldk = f.ldk;
+  T* kf = f.kf;
+  for (int c0 = 0; c0 < f.np; c0 += NB2) {
+    const int c1 = std::min(c0 + NB2, f.np);
+    // (1) panel: 128-wide blocks; updates stay inside the panel's columns
+    for (int k0 = c0; k0 < c1; k0 += NB) {
+      T* dk = f.dinv + static_cast<long>(k0) * NB;
+      {
+        ProfScope prof(s, RAD_PROF_DIAG_INVERSE, 2.0 * NB * NB * NB, 0.0);
+        hipLaunchKernelGGL(gj_inverse<T>, dim3(1), dim3(GJ_THREADS), 0, s,
+                           kf + static_cast<long>(k0) * ldk + k0, ldk, dk, sc);
+      }
+      const int r1 = k0 + NB;
+      if (r1 >= f.np) break;
+      T* x = kf + static_cast<long>(r1) * ldk + k0;
+      GemmArgs<T> a = gemm_args<T>(x, ldk, f.np - r1, NB, T(1), T(0));
+      gemm_add_segment<T>(a, dk, NB, x, ldk, NB);
+      RAD_GEMM(a, false);
+      if (r1 < c1) {
+        GemmArgs<T> u = update_args<T>(x, ldk, f.np - r1, NB);
+        gemm_add_segment<T>(u, kf + static_cast<long>(k0) * ldk + r1, ldk, kf + static_cast<long>(r1) * ldk + r1,
+                            ldk, c1 - r1);
+        RAD_GEMM(u, false);
+      }
     }
-    if (k + 1 == f.P) break;
-    const long r1 = r0 + NB;
-    const int m = f.np - static_cast<int>(r1);
-    T* a21 = f.kf + r1 * f.ldk + r0;
-    GemmArgs<T> x = gemm_args<T>(a21, f.ldk, m, NB, T(1), T(0));
-    gemm_add_segment<T>(x, dk, NB, a21, f.ldk, NB);
-    RAD_GEMM(x, false);
-    GemmArgs<T> t = gemm_args<T>(a21, f.ldk, m, NB, T(-1), T(1));
-    gemm_add_segment<T>(t, f.kf + r0 * f.ldk + r1, f.ldk, f.kf + r1 * f.ldk + r1, f.ldk, m);
-    if (Y) gemm_add_segment<T>(t, Y + r0 * ldy, ldy, Y + r1 * ldy, ldy, wy);
-    RAD_GEMM(t, false);
+    // (2) the panel's rows to the right of the panel: block forward substitution
+    for (int k0 = c0; k0 + NB < c1; k0 += NB) {
+      const int r1 = k0 + NB;
+      GemmArgs<T> u = update_args<T>(kf + static_cast<long>(r1) * ldk + k0, ldk, c1 - r1, NB);
+      if (c1 < f.np)
+        gemm_add_segment<T>(u, kf + static_cast<long>(k0) * ldk + c1, ldk, kf + static_cast<long>(r1) * ldk + c1,
+                            ldk, f.np - c1);
+      if (Y) gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
+      if (u.nseg) RAD_GEMM(u, false);
+    }
+    // (3) everything below and right of the panel: one K = panel-width GEMM
+    if (c1 < f.np) {
+      GemmArgs<T> u = update_args<T>(kf + static_cast<long>(c1) * ldk + c0, ldk, f.np - c1, c1 - c0);
+      gemm_add_segment<T>(u, kf + static_cast<long>(c0) * ldk + c1, ldk, kf + static_cast<long>(c1) * ldk + c1,
+                          ldk, f.np - c1);
+      if (Y) gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+      RAD_GEMM(u, false);
+    }
   }
   return hipGetLastError();
 }
 
-// Y <- L^{-1} Y with the stored factors (for refinement right-hand sides).
+// Y <- L^{-1} Y with the stored factors (refinement right-hand sides).
 template <class T>
 hipError_t forward_only(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
-  for (int k = 0; k + 1 < f.P; ++k) {
-    const long r0 = static_cast<long>(k) * NB, r1 = r0 + NB;
-    GemmArgs<T> t = gemm_args<T>(f.kf + r1 * f.ldk + r0, f.ldk, f.np - static_cast<int>(r1), NB, T(-1), T(1));
-    gemm_add_segment<T>(t, Y + r0 * ldy, ldy, Y + r1 * ldy, ldy, wy);
-    RAD_GEMM(t, false);
+  const long ldk = f.ldk;
+  for (int c0 = 0; c0 < f.np; c0 += NB2) {
+    const int c1 = std::min(c0 + NB2, f.np);
+    for (int k0 = c0; k0 + NB < c1; k0 += NB) {
+      const int r1 = k0 + NB;
+      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(r1) * ldk + k0, ldk, c1 - r1, NB);
+      gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
+      RAD_GEMM(u, false);
+    }
+    if (c1 < f.np) {
+      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c1) * ldk + c0, ldk, f.np - c1, c1 - c0);
+      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+      RAD_GEMM(u, false);
+    }
   }
   return hipSuccess;
 }
 
-// Out <- U^{-1} Y.  Out may alias Y.  Only the first n rows are formed.
+// Y <- U^{-1} Y in place (all np rows; padded rows stay zero).
 template <class T>
-hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* Out, long ldo, hipStream_t s) {
-  for (int k = f.P - 1; k >= 0; --k) {
-    const long r0 = static_cast<long>(k) * NB;
-    const int kk = std::min<int>(NB, f.n - static_cast<int>(r0));
-    GemmArgs<T> d = gemm_args<T>(f.dinv + r0 * NB, NB, kk, kk, T(1), T(0));
-    gemm_add_segment<T>(d, Y + r0 * ldy, ldy, Out + r0 * ldo, ldo, wy);
-    RAD_GEMM(d, false);
-    if (k == 0) break;
-    GemmArgs<T> u = gemm_args<T>(f.kf + r0, f.ldk, static_cast<int>(r0), kk, T(-1), T(1));
-    gemm_add_segment<T>(u, Out + r0 * ldo, ldo, Y, ldy, wy);
-    RAD_GEMM(u, false);
+hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
+  const long ldk = f.ldk;
+  const int last_c0 = ((f.np - 1) / NB2) * NB2;
+  for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
+    const int c1 = std::min(c0 + NB2, f.np);
+    for (int k0 = c1 - NB; k0 >= c0; k0 -= NB) {
+      GemmArgs<T> d = gemm_args<T>(f.dinv + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
+      gemm_add_segment<T>(d, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(k0) * ldy, ldy, wy);
+      RAD_GEMM(d, false);
+      if (k0 > c0) {
+        GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + k0, ldk, k0 - c0, NB);
+        gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(c0) * ldy, ldy, wy);
+        RAD_GEMM(u, false);
+      }
+    }
+    if (c0 > 0) {
+      GemmArgs<T> u = update_args<T>(f.kf + c0, ldk, c0, c1 - c0);
+      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
+      RAD_GEMM(u, false);
+    }
   }
   return hipSuccess;
 }
 
-// Lambda <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z.
+// Y <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z.
 template <class T>
 hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
-  for (int k = 0; k < f.P; ++k) {
-    const long r0 = static_cast<long>(k) * NB;
-    // Z_k = D_k^{-T} Y_k
-    GemmArgs<T> d = gemm_args<T>(f.dinv + r0 * NB, NB, NB, NB, T(1), T(0));
-    gemm_add_segment<T>(d, Y + r0 * ldy, ldy, Y + r0 * ldy, ldy, wy);
-    RAD_GEMM(d, true);
-    if (k + 1 == f.P) break;
-    const long r1 = r0 + NB;
-    // Y_below -= (U_{k, below})^T Z_k
-    GemmArgs<T> u = gemm_args<T>(f.kf + r0 * f.ldk + r1, f.ldk, f.np - static_cast<int>(r1), NB, T(-1), T(1));
-    gemm_add_segment<T>(u, Y + r0 * ldy, ldy, Y + r1 * ldy, ldy, wy);
-    RAD_GEMM(u, true);
+  const long ldk = f.ldk;
+  // U^T Z = Y: forward over blocks
+  for (int c0 = 0; c0 < f.np; c0 += NB2) {
+    const int c1 = std::min(c0 + NB2, f.np);
+    for (int k0 = c0; k0 < c1; k0 += NB) {
+      GemmArgs<T> d = gemm_args<T>(f.dinv + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
+      gemm_add_segment<T>(d, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(k0) * ldy, ldy, wy);
+      RAD_GEMM(d, true);
+      const int r1 = k0 + NB;
+      if (r1 < c1) {  // rows of the panel below block k: (U_{k, r1..c1})^T Z_k
+        GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(k0) * ldk + r1, ldk, c1 - r1, NB);
+        gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
+        RAD_GEMM(u, true);
+      }
+    }
+    if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
+      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + c1, ldk, f.np - c1, c1 - c0);
+      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+      RAD_GEMM(u, true);
+    }
   }
-  for (int k = f.P - 1; k >= 1; --k) {
-    const long r0 = static_cast<long>(k) * NB;
-    // Y_above -= (X_{k, above})^T Lambda_k
-    GemmArgs<T> x = gemm_args<T>(f.kf + r0 * f.ldk, f.ldk, static_cast<int>(r0), NB, T(-1), T(1));
-    gemm_add_segment<T>(x, Y + r0 * ldy, ldy, Y, ldy, wy);
-    RAD_GEMM(x, true);
+  // L^T Lambda = Z: backward over blocks (unit diagonal)
+  const int last_c0 = ((f.np - 1) / NB2) * NB2;
+  for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
+    const int c1 = std::min(c0 + NB2, f.np);
+    for (int k0 = c1 - NB; k0 > c0; k0 -= NB) {  // rows of the panel above block k
+      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(k0) * ldk + c0, ldk, k0 - c0, NB);
+      gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(c0) * ldy, ldy, wy);
+      RAD_GEMM(u, true);
+    }
+    if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
+      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk, ldk, c0, c1 - c0);
+      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
+      RAD_GEMM(u, true);
+    }
   }
   return hipSuccess;
 }
@@ -466,10 +583,12 @@ struct GebWork {
   Scalars* sc;
   void* y;      // RHS / solution (T), np x ldy
   long ldy;
-  double* r;    // FP64 residual (n x ldr), refinement only
-  long ldr;
-  double* lam;  // FP64 Lambda (adjoint refinement when the caller gives none)
-  long ldl;
+  double* x;    // FP64 iterate (np x ldx), refinement only
+  long ldx;
+  double* r;    // FP64 residual (np x ldx)
+  double* p;    // FP64 P = F_sq diag(rho) (np x ldp), refinement only
+  long ldp;
+  double* part; // grad_eps partial sums (adjoint)
   size_t bytes;
   bool ok;
 };
@@ -485,13 +604,13 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
   } else {
     w.ldy = rhs_ld(n, pad_elems<float>());
     w.y = cv.take<float>(static_cast<size_t>(np) * w.ldy);
-    w.ldr = static_cast<long>(ceil_div(n + 1, 16) * 16);
-    w.r = cv.take<double>(static_cast<size_t>(n) * w.ldr);
-    if (adjoint) {
-      w.ldl = w.ldr;
-      w.lam = cv.take<double>(static_cast<size_t>(n) * w.ldl);
-    }
+    w.ldx = rhs_ld(n, pad_elems<double>());
+    w.x = cv.take<double>(static_cast<size_t>(np) * w.ldx);
+    w.r = cv.take<double>(static_cast<size_t>(np) * w.ldx);
+    w.ldp = static_cast<long>(np + pad_elems<double>());
+    w.p = cv.take<double>(static_cast<size_t>(np) * w.ldp);
   }
+  if (adjoint) w.part = cv.take<double>(static_cast<size_t>(ceil_div(n, GE_ROWS) * n));
   w.bytes = cv.used;
   w.ok = cv.ok;
   return w;
@@ -507,14 +626,10 @@ int read_scalars(Scalars* dev, Scalars* host, hipStream_t s) {
   return RAD_OK;
 }
 
-// FP64 residual R = E - K X = (E - X) + F_sq diag(rho) X  (X n x (n+1) fp64)
-hipError_t residual64(const double* F, long ldf, int n, const double* eps, const double* rho,
-                      const double* X, long ldx, double* R, long ldr, hipStream_t s) {
-  hipLaunchKernelGGL(residual_init, dim3(n), dim3(256), 0, s, F, ldf, n, eps, X, ldx, R, ldr);
-  GemmArgs<double> a = gemm_args<double>(F, ldf, n, n, 1.0, 1.0);
-  a.colscale = rho;
-  gemm_add_segment<double>(a, X, ldx, R, ldr, n + 1);
-  return launch_gemm(a, false, s);
+template <class T>
+void zero(T* p, long count, hipStream_t s) {
+  const long blocks = std::min<long>(ceil_div(count, 256), 8192);
+  hipLaunchKernelGGL(fill_zero<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, count);
 }
 
 }  // namespace
@@ -556,36 +671,47 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
   int ir_steps = 0;
   Scalars h{};
   if (precision == RAD_PREC_FP64) {
-    FactorLayout fl = factor_layout<double>(n);
-    Fact<double> f = make_fact<double>(factors, fl);
+    Fact<double> f = make_fact<double>(factors, factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
     hipLaunchKernelGGL(geb_form<double>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
-                       rho, f.kf, f.ldk, f.np, Y, w.ldy, ni + 1, w.sc);
+                       rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
     RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s));
-    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, B, static_cast<long>(ldb), s));
+    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, s));
+    hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
+                       static_cast<long>(ldb));
   } else {
-    FactorLayout fl = factor_layout<float>(n);
-    Fact<float> f = make_fact<float>(factors, fl);
+    Fact<float> f = make_fact<float>(factors, factor_layout<float>(n));
     float* Y = static_cast<float*>(w.y);
     hipLaunchKernelGGL(geb_form<float>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
-                       rho, f.kf, f.ldk, f.np, Y, w.ldy, ni + 1, w.sc);
+                       rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
     RAD_HIP_CHECK(factor_forward<float>(f, Y, w.ldy, ni + 1, w.sc, s));
-    RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, Y, w.ldy, s));
-    hipLaunchKernelGGL(store_solution<float>, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
-                       static_cast<long>(ldb));
-    for (int step = 0; step < ir_max; ++step) {
-      hipLaunchKernelGGL(scalars_init_partial, dim3(1), dim3(64), 0, s, w.sc);
-      RAD_HIP_CHECK(residual64(F, static_cast<long>(ldf), ni, eps, rho, B, static_cast<long>(ldb), w.r,
-                               w.ldr, s));
-      hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldr, ni, Y, w.ldy, w.sc);
-      RAD_HIP_CHECK(forward_only<float>(f, Y, w.ldy, ni + 1, s));
-      RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, Y, w.ldy, s));
-      hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
-                         static_cast<long>(ldb), w.sc);
-      ++ir_steps;
-      int rc = read_scalars(w.sc, &h, s);
-      if (rc != RAD_OK) return rc;
-      if (h.status < 0 || h.max_d <= ir_tol) break;
+    RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, s));
+    if (ir_max > 0) {
+      zero<double>(w.x, static_cast<long>(f.np) * w.ldx, s);
+      zero<double>(w.r, static_cast<long>(f.np) * w.ldx, s);
+      hipLaunchKernelGGL(form_p64, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, rho, w.p, w.ldp);
+      hipLaunchKernelGGL((copy_block<float, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx);
+      for (int step = 0; step < ir_max; ++step) {
+        hipLaunchKernelGGL(scalars_init_partial, dim3(1), dim3(64), 0, s, w.sc);
+        hipLaunchKernelGGL(residual_init, dim3(ni), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps, w.x,
+                           w.ldx, w.r, w.ldx);
+        GemmArgs<double> a = gemm_args<double>(w.p, w.ldp, ni, static_cast<int>(ceil_div(n, 32) * 32), 1.0, 1.0);
+        gemm_add_segment<double>(a, w.x, w.ldx, w.r, w.ldx, ni + 1);
+        RAD_HIP_CHECK(launch_gemm(a, false, s));
+        hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldx, ni, Y, w.ldy, w.sc);
+        RAD_HIP_CHECK(forward_only<float>(f, Y, w.ldy, ni + 1, s));
+        RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, s));
+        hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx, w.sc);
+        ++ir_steps;
+        int rc = read_scalars(w.sc, &h, s);
+        if (rc != RAD_OK) return rc;
+        if (h.status < 0 || h.max_d <= ir_tol) break;
+      }
+      hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, w.x, w.ldx, ni, B,
+                         static_cast<long>(ldb));
+    } else {
+      hipLaunchKernelGGL((copy_block<float, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
+                         static_cast<long>(ldb));
     }
   }
   RAD_HIP_CHECK(hipGetLastError());
@@ -669,49 +795,50 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
   int ir_steps = 0;
   Scalars h{};
   if (precision == RAD_PREC_FP64) {
-    FactorLayout fl = factor_layout<double>(n);
-    Fact<double> f = make_fact<double>(const_cast<void*>(factors), fl);
+    Fact<double> f = make_fact<double>(const_cast<void*>(factors), factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
-    hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y,
-                       w.ldy, ni + 1);
+    hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
     RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, s));
     lam = Y;
     ldlam = w.ldy;
-    if (Lambda)
-      hipLaunchKernelGGL(copy_out<double>, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, Lambda,
-                         static_cast<long>(ldl));
   } else {
-    FactorLayout fl = factor_layout<float>(n);
-    Fact<float> f = make_fact<float>(const_cast<void*>(factors), fl);
+    Fact<float> f = make_fact<float>(const_cast<void*>(factors), factor_layout<float>(n));
     float* Y = static_cast<float*>(w.y);
-    double* L64 = Lambda ? Lambda : w.lam;
-    const long ld64 = Lambda ? static_cast<long>(ldl) : w.ldl;
-    hipLaunchKernelGGL(load_rhs<float>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y,
-                       w.ldy, ni + 1);
+    hipLaunchKernelGGL(load_rhs<float>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
     RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, s));
-    hipLaunchKernelGGL(store_solution<float>, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, L64, ld64);
+    zero<double>(w.x, static_cast<long>(f.np) * w.ldx, s);
+    hipLaunchKernelGGL((copy_block<float, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx);
+    if (ir_max > 0) {
+      zero<double>(w.r, static_cast<long>(f.np) * w.ldx, s);
+      hipLaunchKernelGGL(form_p64, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, rho, w.p, w.ldp);
+    }
     for (int step = 0; step < ir_max; ++step) {
       hipLaunchKernelGGL(scalars_init_partial, dim3(1), dim3(64), 0, s, w.sc);
-      // R = G - K^T Lambda = (G - Lambda) + diag(rho) F_sq^T Lambda
-      hipLaunchKernelGGL(adj_residual_init, dim3(ni), dim3(256), 0, s, G, static_cast<long>(ldg), ni, L64,
-                         ld64, w.r, w.ldr);
-      GemmArgs<double> a = gemm_args<double>(F, static_cast<long>(ldf), ni, ni, 1.0, 1.0);
-      a.rowscale = rho;
-      gemm_add_segment<double>(a, L64, ld64, w.r, w.ldr, ni + 1);
+      // R = G - K^T Lambda = (G - Lambda) + P^T Lambda
+      hipLaunchKernelGGL(adj_residual_init, dim3(ni), dim3(256), 0, s, G, static_cast<long>(ldg), ni, w.x,
+                         w.ldx, w.r, w.ldx);
+      GemmArgs<double> a = gemm_args<double>(w.p, w.ldp, ni, static_cast<int>(ceil_div(n, 32) * 32), 1.0, 1.0);
+      gemm_add_segment<double>(a, w.x, w.ldx, w.r, w.ldx, ni + 1);
       RAD_HIP_CHECK(launch_gemm(a, true, s));
-      hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldr, ni, Y, w.ldy, w.sc);
+      hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldx, ni, Y, w.ldy, w.sc);
       RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, s));
-      hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, L64, ld64, w.sc);
+      hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx, w.sc);
       ++ir_steps;
       int rc = read_scalars(w.sc, &h, s);
       if (rc != RAD_OK) return rc;
       if (h.max_d <= ir_tol) break;
     }
-    lam = L64;
-    ldlam = ld64;
+    lam = w.x;
+    ldlam = w.ldx;
   }
-  hipLaunchKernelGGL(adj_grad_eps, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, lam,
-                     ldlam, F, static_cast<long>(ldf), ni, grad_eps);
+  if (Lambda)
+    hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, lam, ldlam, ni, Lambda,
+                       static_cast<long>(ldl));
+  const int chunks = static_cast<int>(ceil_div(n, GE_ROWS));
+  hipLaunchKernelGGL(adj_grad_eps_partial, dim3(static_cast<unsigned>(ceil_div(n, 256)), chunks), dim3(256), 0, s,
+                     lam, ldlam, F, static_cast<long>(ldf), ni, w.part);
+  hipLaunchKernelGGL(adj_grad_eps_final, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, w.part,
+                     ni, chunks, grad_eps);
   hipLaunchKernelGGL(adj_grad_rho, dim3(static_cast<unsigned>(ceil_div(n, 4))), dim3(256), 0, s, lam, ldlam,
                      G, static_cast<long>(ldg), B, static_cast<long>(ldb), rho, ni, grad_rho);
   hipLaunchKernelGGL(adj_grad_rho_direct, dim3(ni), dim3(256), 0, s, lam, ldlam, F, static_cast<long>(ldf),

@@ -1,19 +1,14 @@
 // MFMA GEMM building block for the dense solves (FP64 and FP32 on gfx950).
 //
-//   C[seg] = beta * C[seg] + alpha * rowscale .* (op(A) .* colscale) * B[seg]
+//   C[seg] = beta * C[seg] + alpha * op(A) * B[seg]
 //
 // op(A) is M x K (row-major A, or the transpose of a row-major K x M array);
 // B and C are row-major.  The columns of C may span two segments with their
 // own base pointers (used to update a factor matrix and its right-hand sides
-// in one launch).  All bounds are checked, so ragged shapes are fine.
+// in one launch).
 //
 // Tiling: a 256-thread workgroup computes a 128 x 128 tile; each of its four
-// waves owns 64 x 64 = 4 x 4 blocks of v_mfma_{f64,f32}_16x16x4.  Fragments
-// are loaded straight from global memory into registers (no LDS): within a
-// 16-wide K chunk, lane group g = lane / 16 takes k = 4g + s at MFMA step s,
-// so each lane reads 4 consecutive K entries of a row of A and every 16-lane
-// group reads 16 consecutive entries of a row of B.  The next chunk is loaded
-// while the current one is multiplied.
+// waves owns 64 x 64 = 4 x 4 blocks of v_mfma_{f64,f32}_16x16x4.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,8 +45,6 @@ struct GemmArgs {
   const T* A;
   long lda;
   int M, K;
-  const T* colscale;   // length K or null: op(A)[:, k] *= colscale[k]
-  const T* rowscale;   // length M or null: product row i *= rowscale[i]
   T alpha, beta;
   int nseg;
   int ntile[2];        // 128-wide column tiles per segment
@@ -63,11 +56,106 @@ struct GemmArgs {
 };
 
 constexpr int GEMM_TILE = 128;
-constexpr int GEMM_KC = 16;
+
+// C tile epilogue: C = beta C + alpha acc, stores masked to M x N.
+template <class T>
+__device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[4][4], const GemmArgs<T>& g,
+                                           T* __restrict__ Cm, long ldc, int M, int N, int wr0, int wc0,
+                                           int l) {
+  const int li = l & 15;
+  const bool full = (wr0 + 64 <= M) && (wc0 + 64 <= N);
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wr0 + rb * 16 + Mfma<T>::orow(l, r);
+        const int j = wc0 + cb * 16 + li;
+        if (full || (i < M && j < N)) {
+          T v = g.alpha * acc[rb][cb][r];
+          T* p = Cm + static_cast<long>(i) * ldc + j;
+          if (g.beta != T(0)) v += g.beta * *p;
+          *p = v;
+        }
+      }
+}
+
+// The workgroup stages each 128 x KC slab of op(A) and KC x 128 slab of B
+// once, with 16-byte global loads, into double-buffered LDS; the four waves
+// read their MFMA fragments from LDS.  Within a K chunk, lane group g takes
+// k = g KC/4 + s at MFMA step s.  One barrier per chunk.
+//
+// Operand contract (all operands are the solver's own padded buffers):
+// op(A) is readable for rows < roundup(M, 128) and k < roundup(K, 32), B for
+// rows < roundup(K, 32) and columns < roundup(N, 128); entries with k >= K
+// are zero.  Base pointers and leading dimensions are 16-byte aligned.  Only
+// the stores are masked.
+// K chunk per LDS stage: FP64 uses 16 (2 x 32 KB stages), FP32 32 (2 x 17 KB),
+// so two workgroups share a CU and one's epilogue overlaps the other's MFMAs.
+template <class T>
+struct GemmCfg {
+  static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
+  static constexpr int PA = 2;   // row padding of the A slab (elements)
+  static constexpr int PB = 2;   // row padding of the B slab (elements)
+  static constexpr int EPT = KC / 2;  // slab elements per thread per operand
+};
+
+template <class T, int NE>
+__device__ __forceinline__ void loadv(const T* __restrict__ src, T (&r)[NE]) {
+  typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int per = 16 / sizeof(T);
+  const v2* p = reinterpret_cast<const v2*>(src);
+#pragma unroll
+  for (int q = 0; q < NE / per; ++q) {
+    v2 x = p[q];
+#pragma unroll
+    for (int e = 0; e < per; ++e) r[q * per + e] = x[e];
+  }
+}
 
 template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) gemm_mfma(GemmArgs<T> g) {
+__device__ __forceinline__ void lds_stage_load(const T* __restrict__ A, long lda, const T* __restrict__ Bm,
+                                               long ldb, int m0, int n0, int kc, T (&ra)[GemmCfg<T>::EPT],
+                                               T (&rb)[GemmCfg<T>::EPT]) {
+  constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
+  constexpr int TPR = GEMM_TILE / E;  // threads per 128-wide slab row
+  const int t = threadIdx.x;
+  if (!TRANS_A)  // thread -> op(A) row t/2, E consecutive k
+    loadv<T, E>(A + static_cast<long>(m0 + (t >> 1)) * lda + kc + (t & 1) * E, ra);
+  else           // op(A)[m][k] = At[k][m]: thread -> k row t/TPR, E consecutive m
+    loadv<T, E>(A + static_cast<long>(kc + t / TPR) * lda + m0 + (t % TPR) * E, ra);
+  loadv<T, E>(Bm + static_cast<long>(kc + t / TPR) * ldb + n0 + (t % TPR) * E, rb);
+  (void)KC;
+}
+
+template <class T, bool TRANS_A>
+__device__ __forceinline__ void lds_stage_store(T (*sA)[GemmCfg<T>::KC + GemmCfg<T>::PA],
+                                                T (*sB)[GEMM_TILE + GemmCfg<T>::PB],
+                                                const T (&ra)[GemmCfg<T>::EPT], const T (&rb)[GemmCfg<T>::EPT]) {
+  constexpr int E = GemmCfg<T>::EPT;
+  constexpr int TPR = GEMM_TILE / E;
+  const int t = threadIdx.x;
+  if (!TRANS_A) {
+    const int m = t >> 1, k0 = (t & 1) * E;
+#pragma unroll
+    for (int q = 0; q < E; ++q) sA[m][k0 + q] = ra[q];
+  } else {
+    const int k = t / TPR, mb = (t % TPR) * E;
+#pragma unroll
+    for (int q = 0; q < E; ++q) sA[mb + q][k] = ra[q];
+  }
+  const int k = t / TPR, nb = (t % TPR) * E;
+#pragma unroll
+  for (int q = 0; q < E; ++q) sB[k][nb + q] = rb[q];
+}
+
+template <class T, bool TRANS_A>
+__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
   typedef typename Mfma<T>::v4 v4;
+  constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
+  __shared__ T sA[2][GEMM_TILE][KC + GemmCfg<T>::PA];
+  __shared__ T sB[2][KC][GEMM_TILE + GemmCfg<T>::PB];
   int ct = blockIdx.x;
   int seg = 0;
   if (ct >= g.ntile[0]) {
@@ -77,13 +165,13 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) gemm_mfma(GemmArg
   const T* __restrict__ Bm = g.B[seg];
   T* __restrict__ Cm = g.C[seg];
   const long ldb = g.ldb[seg], ldc = g.ldc[seg];
-  const int N = g.N[seg], M = g.M, K = g.K;
   const T* __restrict__ A = g.A;
   const long lda = g.lda;
+  const int N = g.N[seg], M = g.M, K = g.K;
+  const int m0 = blockIdx.y * GEMM_TILE, n0 = ct * GEMM_TILE;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int li = l & 15, lg = l >> 4;
-  const int wr0 = blockIdx.y * GEMM_TILE + (wave >> 1) * 64;
-  const int wc0 = ct * GEMM_TILE + (wave & 1) * 64;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
 
   v4 acc[4][4];
 #pragma unroll
@@ -91,73 +179,33 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? 1 : 2) gemm_mfma(GemmArg
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  T fa[4][4], fb[4][4], na[4][4], nb[4][4];
-  auto load = [&](int kc, T (&xa)[4][4], T (&xb)[4][4]) {
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int i = wr0 + rb * 16 + li;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = kc + 4 * lg + s;
-        T v = T(0);
-        if (i < M && k < K) {
-          v = TRANS_A ? A[static_cast<long>(k) * lda + i] : A[static_cast<long>(i) * lda + k];
-          if (g.colscale) v *= g.colscale[k];
-        }
-        xa[rb][s] = v;
-      }
-    }
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int j = wc0 + cb * 16 + li;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = kc + 4 * lg + s;
-        xb[cb][s] = (j < N && k < K) ? Bm[static_cast<long>(k) * ldb + j] : T(0);
-      }
-    }
-  };
-
-  load(0, fa, fb);
-  for (int kc = 0; kc < K; kc += GEMM_KC) {
-    const bool more = kc + GEMM_KC < K;
-    if (more) load(kc + GEMM_KC, na, nb);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = Mfma<T>::mma(fa[rb][s], fb[cb][s], acc[rb][cb]);
-    if (more) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          fa[a][s] = na[a][s];
-          fb[a][s] = nb[a][s];
-        }
-    }
-  }
-  // C may alias A or B (in-place block products): every wave must finish
-  // reading before any wave writes.
+  T ra[E], rb[E];
+  const int nch = (K + KC - 1) / KC;
+  lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, 0, ra, rb);
+  lds_stage_store<T, TRANS_A>(sA[0], sB[0], ra, rb);
   __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nch;
+    if (more) lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, (c + 1) * KC, ra, rb);
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = lg * (KC / 4) + s;
+      T fa[4], fb[4];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = wr0 + rb * 16 + Mfma<T>::orow(l, r);
-        const int j = wc0 + cb * 16 + li;
-        if (i < M && j < N) {
-          T v = acc[rb][cb][r];
-          if (g.rowscale) v *= g.rowscale[i];
-          v *= g.alpha;
-          T* p = Cm + static_cast<long>(i) * ldc + j;
-          if (g.beta != T(0)) v += g.beta * *p;
-          *p = v;
-        }
+      for (int q = 0; q < 4; ++q) {
+        fa[q] = sA[buf][wr + q * 16 + li][k];
+        fb[q] = sB[buf][k][wc + q * 16 + li];
       }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = Mfma<T>::mma(fa[x], fb[y], acc[x][y]);
+    }
+    if (more) lds_stage_store<T, TRANS_A>(sA[buf ^ 1], sB[buf ^ 1], ra, rb);
+    __syncthreads();
+  }
+  store_tile<T>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
 }
 
 // Host-side launcher: one or two column segments.
@@ -177,9 +225,9 @@ inline hipError_t launch_gemm(const GemmArgs<T>& a0, bool trans_a, hipStream_t s
   ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32,
                  2.0 * a.M * ncols * a.K, 0.0);
   if (trans_a)
-    hipLaunchKernelGGL((gemm_mfma<T, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_lds<T, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_mfma<T, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((gemm_lds<T, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
