@@ -193,6 +193,67 @@ int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                             double* group_weight, void* work, size_t work_bytes,
                             rad_stats* stats, void* stream);
 
+/* ---- batches of models ------------------------------------------------ */
+/*
+ * Many independent open models of uneven size, each with one or two spectral
+ * bands (e.g. solar and infrared optical properties), enforced and solved
+ * together: the same enforcement iteration as rad_enforce_vf (Sec. 3.5.5) on
+ * every instance, then the Gebhart REF solve of App. B.2 (eq. B.6-B.11) for
+ * every (instance, band), with one kernel launch per step of the shared
+ * elimination schedule instead of one per instance.
+ *
+ * rad_instance (host struct) describes one model; its pointers are device
+ * pointers and must stay valid while the plan is used:
+ *   F      n x (n+1) view factors (ld ldf >= n+1), enforced in place;
+ *   area   n face areas > 0;  n_rays  n ray counts (required for FRACVAR);
+ *   bands  1 or 2;  eps[b], rho[b]  n optical properties of band b;
+ *   B[b]   n x (n+1) output REF matrix of band b (ld ldb[b] >= n+1).
+ *
+ * rad_batch_plan_create (host only, no device work) copies the instance list,
+ * lays out the workspace and builds the launch schedule; *work_bytes receives
+ * the workspace size.  rad_batch_prepare uploads the schedule's descriptor
+ * tables into ``work`` (256-byte aligned, >= work_bytes) and waits for the
+ * copy.  rad_batch_run then only enqueues kernels on ``stream`` and never
+ * synchronizes or copies, so a capture of it in a HIP graph replays the whole
+ * batch: enforce_iters enforcement iterations (an instance whose closure
+ * defect max_i |s_i - 1| falls to enforce_tol > 0 stops early, decided on the
+ * device; enforce_iters = 0 skips enforcement and solves F as given), then
+ * the solves, with ir_steps FP64 refinement steps in RAD_PREC_FP32_IR mode
+ * (ignored for RAD_PREC_FP64).  rad_batch_stats (host) waits for ``stream``
+ * and fills out[0..count) per instance: iters, converged, closure_defect,
+ * recip_err of the enforcement, the largest ir_residual / ir_correction over
+ * the bands, device_status; it returns the most negative device status.
+ * The workspace holds the plan's state: one run at a time per workspace.
+ * rad_batch_plan_destroy frees the host plan (not the workspace).
+ */
+typedef struct rad_instance {
+  double* F;
+  int64_t n;
+  int64_t ldf;
+  const double* area;
+  const double* n_rays;
+  int32_t bands;
+  int32_t reserved;
+  const double* eps[2];
+  const double* rho[2];
+  double* B[2];
+  int64_t ldb[2];
+} rad_instance;
+
+typedef struct rad_batch_plan rad_batch_plan;
+
+int32_t rad_batch_plan_create(const rad_instance* inst, int32_t count,
+                              int32_t precision, int32_t kappa_mode,
+                              rad_batch_plan** plan, size_t* work_bytes);
+int32_t rad_batch_prepare(rad_batch_plan* plan, void* work, size_t work_bytes,
+                          void* stream);
+int32_t rad_batch_run(const rad_batch_plan* plan, void* work,
+                      double enforce_tol, int32_t enforce_iters,
+                      int32_t ir_steps, void* stream);
+int32_t rad_batch_stats(const rad_batch_plan* plan, const void* work,
+                        rad_stats* out, void* stream);
+void rad_batch_plan_destroy(rad_batch_plan* plan);
+
 /* ---- kernel profiling --------------------------------------------------- */
 /*
  * Optional per-launch timing with HIP events, for measuring the hot kernels

@@ -52,6 +52,23 @@ class RadKernelProfile(ctypes.Structure):
     ]
 
 
+class RadInstance(ctypes.Structure):
+    """One model of a batch (struct rad_instance); pointers are device addresses."""
+    _fields_ = [
+        ("F", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("ldf", ctypes.c_int64),
+        ("area", ctypes.c_void_p),
+        ("n_rays", ctypes.c_void_p),
+        ("bands", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("eps", ctypes.c_void_p * 2),
+        ("rho", ctypes.c_void_p * 2),
+        ("B", ctypes.c_void_p * 2),
+        ("ldb", ctypes.c_int64 * 2),
+    ]
+
+
 PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate"]
 
 
@@ -85,6 +102,12 @@ SIGNATURES = {
                                       _I64, _D, _I32, _P, _SZ, _STATS, _P]),
     "rad_aggregate_workspace_bytes": (_SZ, [_I64, _I64]),
     "rad_aggregate_nodes": (_I32, [_P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _SZ, _STATS, _P]),
+    "rad_batch_plan_create": (_I32, [ctypes.POINTER(RadInstance), _I32, _I32, _I32, ctypes.POINTER(_P),
+                                     ctypes.POINTER(_SZ)]),
+    "rad_batch_prepare": (_I32, [_P, _P, _SZ, _P]),
+    "rad_batch_run": (_I32, [_P, _P, _D, _I32, _I32, _P]),
+    "rad_batch_stats": (_I32, [_P, _P, _STATS, _P]),
+    "rad_batch_plan_destroy": (None, [_P]),
     "rad_profile_enable": (_I32, [_I32]),
     "rad_profile_read": (_I32, [ctypes.POINTER(RadKernelProfile), _I32]),
 }

@@ -205,3 +205,70 @@ class GebhartREF(torch.autograd.Function):
         ge, gr, _, _ = gebhart_ref_adjoint(ctx.factors, F.detach(), rho.detach(), B,
                                            G.contiguous(), want_stats=False)
         return None, ge, gr, None
+
+
+class Batch:
+    """Many open models enforced and solved together (rad_batch_*, include/rad.h).
+
+    ``models`` is a list of dicts with keys ``F`` ((n, n+1) float64 CUDA
+    tensor, enforced in place), ``area``, ``n_rays`` (optional for
+    kappa="half"), ``eps`` and ``rho`` (lists of one or two band vectors).
+    The REF matrices land in ``self.B[i][band]``.  ``run`` only enqueues
+    kernels on the current stream, so it may be captured in a CUDA graph.
+    """
+
+    def __init__(self, models, precision: str = "fp32_ir", kappa: str = "fracvar"):
+        if not models:
+            raise ValueError("empty batch")
+        self.device = models[0]["F"].device
+        self._keep = []
+        self.B = []
+        arr = (L.RadInstance * len(models))()
+        for k, m in enumerate(models):
+            F = m["F"]
+            n = F.shape[0]
+            ldf = _mat(F, f"models[{k}].F", n, n + 1)
+            area = _vec(m["area"], "area", n)
+            nr = _vec(m.get("n_rays"), "n_rays", n)
+            eps, rho = list(m["eps"]), list(m["rho"])
+            if not 1 <= len(eps) <= 2 or len(rho) != len(eps):
+                raise ValueError(f"models[{k}]: one or two bands of eps and rho expected")
+            bs = [torch.empty((n, n + 1), dtype=torch.float64, device=self.device) for _ in eps]
+            s = arr[k]
+            s.F, s.n, s.ldf = F.data_ptr(), n, ldf
+            s.area = area.data_ptr()
+            s.n_rays = nr.data_ptr() if nr is not None else None
+            s.bands = len(eps)
+            for b in range(len(eps)):
+                s.eps[b] = _vec(eps[b], "eps", n).data_ptr()
+                s.rho[b] = _vec(rho[b], "rho", n).data_ptr()
+                s.B[b] = bs[b].data_ptr()
+                s.ldb[b] = bs[b].stride(0)
+            self._keep += [F, area, nr, *eps, *rho]
+            self.B.append(bs)
+        self.count = len(models)
+        lib = L.lib()
+        plan = ctypes.c_void_p()
+        wb = ctypes.c_size_t()
+        L.check(lib.rad_batch_plan_create(arr, len(models), _PREC[precision], _KAPPA[kappa], ctypes.byref(plan),
+                                          ctypes.byref(wb)), "rad_batch_plan_create")
+        self._plan = plan
+        self.work = torch.empty(max(int(wb.value), 256), dtype=torch.uint8, device=self.device)
+        L.check(lib.rad_batch_prepare(self._plan, _vp(self.work), self.work.numel(), _stream(self.device)),
+                "rad_batch_prepare")
+
+    def run(self, enforce_iters: int = 0, enforce_tol: float = 0.0, ir_steps: int = 1) -> None:
+        L.check(L.lib().rad_batch_run(self._plan, _vp(self.work), float(enforce_tol), int(enforce_iters),
+                                      int(ir_steps), _stream(self.device)), "rad_batch_run")
+
+    def stats(self):
+        out = (L.RadStats * self.count)()
+        code = L.lib().rad_batch_stats(self._plan, _vp(self.work), out, _stream(self.device))
+        L.check(code, "rad_batch_stats")
+        return [s.as_dict() for s in out]
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan:
+            L.lib().rad_batch_plan_destroy(plan)
+            self._plan = None

@@ -1,0 +1,769 @@
+// Batched radiative pipeline: many open models of uneven size, one or two
+// spectral bands each, enforced and solved together.
+//
+// Enforcement (thesis Sec. 3.5.5) runs all instances in the same grids: the
+// tile pairs, row blocks and rows of every instance are concatenated and each
+// block finds its instance by a binary search over prefix sums; per-instance
+// device flags stop converged instances without host synchronisation.
+//
+// The Gebhart solves (App. B.2) of all (instance, band) problems advance in
+// lockstep through the same two-level block LDU schedule as the single solve;
+// at every schedule step one grouped launch carries the diagonal-block
+// inverses, or the MFMA GEMM tiles, of every problem that has that step.
+// The grouped GEMM is persistent: its grid is capped near the number of
+// resident workgroups and each workgroup walks the tile list.
+//
+// rad_batch_prepare builds the schedule and uploads its descriptor tables
+// once; rad_batch_run only launches kernels, so it can be captured in a HIP
+// graph and replayed.
+#include <cstring>
+#include <vector>
+
+#include "enforce_kernels.h"
+#include "gebhart_kernels.h"
+
+struct rad_batch_plan {
+  int count = 0;
+  int nprob = 0;
+  int precision = RAD_PREC_FP64;
+  int kappa = RAD_KAPPA_FRACVAR;
+  std::vector<rad_instance> inst;
+  size_t work_bytes = 0;
+  void* prepared_for = nullptr;
+  // filled by layout()
+  struct InstOff { size_t ctrl, scale, inv_area, blkmax, partial; int t; long pairs; };
+  struct ProbOff { int inst, band, n, np; long ldk, ldy, ldx, ldp; size_t kf, dinv, y, x, r, p, sc; };
+  std::vector<InstOff> io;
+  std::vector<ProbOff> po;
+  size_t tables_off = 0;
+  // launch schedule (table offsets relative to the tables block)
+  struct Launch { int kind; int trans; unsigned grid; size_t off, off2; int count; double flops; };
+  std::vector<Launch> factor, back, fwd, resid;
+  size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
+  double sweep_bytes = 0.0;  // algorithmic bytes of one sweep over every instance
+  long total_pairs = 0, total_fblk = 0, total_rows = 0, total_nprow = 0, total_nrow = 0;
+};
+
+namespace rad {
+namespace {
+
+enum { L_GJ = 0, L_GEMM = 1 };
+
+struct ProbDesc {
+  const double* F;
+  long ldf;
+  int n, np;
+  const double* eps;
+  const double* rho;
+  double* B;
+  long ldb;
+  void* kf;
+  long ldk;
+  void* dinv;
+  void* y;
+  long ldy;
+  double* x;
+  double* r;
+  long ldx;
+  double* p;
+  long ldp;
+  Scalars* sc;
+};
+
+// ------------------------------------------------ row-flat batched kernels ---
+template <class T>
+__global__ void __launch_bounds__(256)
+b_form(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const int i = static_cast<int>(blockIdx.x - start[q]);
+  const int n = d.n, np = d.np;
+  const double* frow = d.F + static_cast<long>(i) * d.ldf;
+  T* krow = static_cast<T*>(d.kf) + static_cast<long>(i) * d.ldk;
+  T* yrow = static_cast<T*>(d.y) + static_cast<long>(i) * d.ldy;
+  int bad = 0;
+  const long jend = d.ldk > d.ldy ? d.ldk : d.ldy;
+  for (long j = threadIdx.x; j < jend; j += blockDim.x) {
+    double kv = (i == j) ? 1.0 : 0.0;
+    double yv = 0.0;
+    if (i < n && j <= n) {
+      const double f = frow[j];
+      bad |= !(f >= 0.0 && f <= 1.0e300);
+      if (j < n) {
+        kv = kv - f * d.rho[j];
+        yv = f * d.eps[j];
+      } else {
+        yv = f;  // space column: no emissivity factor (eq. B.6)
+      }
+    }
+    if (j < d.ldk) krow[j] = (j < np) ? static_cast<T>(kv) : T(0);
+    if (j < d.ldy) yrow[j] = static_cast<T>(yv);
+  }
+  if (i < n && threadIdx.x == 0) {
+    const double e = d.eps[i], r = d.rho[i];
+    bad |= !(e >= 0.0 && e <= 1.0 && r >= 0.0 && r <= 1.0);
+  }
+  if (bad) raise_status(&d.sc->status, RAD_ENONFINITE);
+}
+
+__global__ void __launch_bounds__(256)
+b_form_p64(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const int i = static_cast<int>(blockIdx.x - start[q]);
+  for (long j = threadIdx.x; j < d.ldp; j += blockDim.x)
+    d.p[static_cast<long>(i) * d.ldp + j] =
+        (i < d.n && j < d.n) ? d.F[static_cast<long>(i) * d.ldf + j] * d.rho[j] : 0.0;
+}
+
+// zero the refinement iterate and residual rows (np rows of ldx)
+__global__ void __launch_bounds__(256)
+b_zero_xr(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const long i = blockIdx.x - start[q];
+  for (long j = threadIdx.x; j < d.ldx; j += blockDim.x) {
+    d.x[i * d.ldx + j] = 0.0;
+    d.r[i * d.ldx + j] = 0.0;
+  }
+}
+
+// which: 0 = Y(T) -> B, 1 = Y(T) -> X64, 2 = X64 -> B      (rows < n, cols <= n)
+template <class T>
+__global__ void __launch_bounds__(256)
+b_copy(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count, int which) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const long i = blockIdx.x - start[q];
+  for (int j = threadIdx.x; j <= d.n; j += blockDim.x) {
+    if (which == 2) {
+      d.B[i * d.ldb + j] = d.x[i * d.ldx + j];
+    } else {
+      const double v = static_cast<double>(static_cast<const T*>(d.y)[i * d.ldy + j]);
+      if (which == 0) d.B[i * d.ldb + j] = v; else d.x[i * d.ldx + j] = v;
+    }
+  }
+}
+
+__global__ void b_scalars_init(const ProbDesc* __restrict__ pd, int count, int full) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  Scalars* sc = pd[q].sc;
+  if (full) sc->status = 0;
+  sc->max_r = 0.0;
+  sc->max_d = 0.0;
+  sc->red[0] = sc->red[1] = 0.0;
+}
+
+// R = E - X  (rows < n, cols <= n)
+__global__ void __launch_bounds__(256)
+b_residual_init(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const long i = blockIdx.x - start[q];
+  const double* f = d.F + i * d.ldf;
+  for (int j = threadIdx.x; j <= d.n; j += blockDim.x) {
+    const double e = (j < d.n) ? f[j] * d.eps[j] : f[d.n];
+    d.r[i * d.ldx + j] = e - d.x[i * d.ldx + j];
+  }
+}
+
+// Y32 <- R, records max |R|
+__global__ void __launch_bounds__(256)
+b_residual_to_rhs(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const long i = blockIdx.x - start[q];
+  float* y = static_cast<float*>(d.y);
+  double m = 0.0;
+  for (int j = threadIdx.x; j <= d.n; j += blockDim.x) {
+    const double v = d.r[i * d.ldx + j];
+    m = fmax(m, fabs(v));
+    y[i * d.ldy + j] = static_cast<float>(v);
+  }
+  block_max(m, &d.sc->max_r);
+}
+
+// X += Y32, records max |delta|
+__global__ void __launch_bounds__(256)
+b_apply_correction(const ProbDesc* __restrict__ pd, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const ProbDesc& d = pd[q];
+  const long i = blockIdx.x - start[q];
+  const float* y = static_cast<const float*>(d.y);
+  double m = 0.0;
+  for (int j = threadIdx.x; j <= d.n; j += blockDim.x) {
+    const double v = static_cast<double>(y[i * d.ldy + j]);
+    m = fmax(m, fabs(v));
+    d.x[i * d.ldx + j] += v;
+  }
+  block_max(m, &d.sc->max_d);
+}
+
+// persistent grouped GEMM: workgroups walk the concatenated tile list
+template <class T, bool TRANS_A>
+__global__ void __launch_bounds__(256, 2)
+gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
+  const int total = tile_start[nprob];
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const GemmArgs<T>& g = probs[lo];
+    const int local = b - tile_start[lo];
+    const int ntx = g.ntile[0] + g.ntile[1];
+    gemm_tile<T, TRANS_A>(g, local % ntx, local / ntx);
+  }
+}
+
+constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU
+
+// ------------------------------------------------------------- host side ---
+struct TableBuilder {
+  std::vector<char> data;
+  template <class X>
+  size_t add(const X* p, size_t n) {
+    size_t off = align_up(data.size(), 256);
+    data.resize(off + sizeof(X) * n);
+    if (n) std::memcpy(data.data() + off, p, sizeof(X) * n);
+    return off;
+  }
+};
+
+template <class T>
+struct Sched {
+  rad_batch_plan* P;
+  char* base;
+  TableBuilder* tb;
+  T* kf(int q) { return reinterpret_cast<T*>(base + P->po[q].kf); }
+  T* dinv(int q) { return reinterpret_cast<T*>(base + P->po[q].dinv); }
+  T* y(int q) { return reinterpret_cast<T*>(base + P->po[q].y); }
+  Scalars* sc(int q) { return reinterpret_cast<Scalars*>(base + P->po[q].sc); }
+
+  void emit_gemm(std::vector<rad_batch_plan::Launch>& out, std::vector<GemmArgs<T>>& a, bool trans) {
+    if (a.empty()) return;
+    std::vector<int> ts(a.size() + 1, 0);
+    double flops = 0.0;
+    for (size_t k = 0; k < a.size(); ++k) {
+      ts[k + 1] = ts[k] + gemm_tiles<T>(a[k]);
+      for (int q = 0; q < a[k].nseg; ++q) flops += 2.0 * a[k].M * a[k].N[q] * a[k].K;
+    }
+    if (ts.back() == 0) {
+      a.clear();
+      return;
+    }
+    rad_batch_plan::Launch L{};
+    L.flops = flops;
+    L.kind = L_GEMM;
+    L.trans = trans ? 1 : 0;
+    L.count = static_cast<int>(a.size());
+    L.off = tb->add(a.data(), a.size());
+    L.off2 = tb->add(ts.data(), ts.size());
+    L.grid = static_cast<unsigned>(std::min<int>(ts.back(), PERSISTENT_GRID));
+    out.push_back(L);
+    a.clear();
+  }
+  void emit_gj(std::vector<rad_batch_plan::Launch>& out, std::vector<GjJob<T>>& j) {
+    if (j.empty()) return;
+    rad_batch_plan::Launch L{};
+    L.kind = L_GJ;
+    L.count = static_cast<int>(j.size());
+    L.grid = static_cast<unsigned>(j.size());
+    L.off = tb->add(j.data(), j.size());
+    out.push_back(L);
+    j.clear();
+  }
+
+  int max_panels() {
+    int m = 0;
+    for (auto& p : P->po) m = std::max(m, static_cast<int>(ceil_div(p.np, NB2)));
+    return m;
+  }
+
+  // factorization with fused forward elimination (same order as factor_forward)
+  void factor() {
+    std::vector<GjJob<T>> gj;
+    std::vector<GemmArgs<T>> g;
+    const int mp = max_panels();
+    for (int pan = 0; pan < mp; ++pan) {
+      for (int kk = 0; kk < NB2 / NB; ++kk) {
+        for (int q = 0; q < P->nprob; ++q) {
+          const auto& o = P->po[q];
+          const int c0 = pan * NB2;
+          if (c0 >= o.np) continue;
+          const int c1 = std::min(c0 + NB2, o.np), k0 = c0 + kk * NB;
+          if (k0 >= c1) continue;
+          gj.push_back(GjJob<T>{kf(q) + static_cast<long>(k0) * o.ldk + k0, o.ldk,
+                                dinv(q) + static_cast<long>(k0) * NB, sc(q)});
+        }
+        emit_gj(P->factor, gj);
+        for (int q = 0; q < P->nprob; ++q) {  // X = A21 D^{-1}
+          const auto& o = P->po[q];
+          const int c0 = pan * NB2;
+          if (c0 >= o.np) continue;
+          const int c1 = std::min(c0 + NB2, o.np), k0 = c0 + kk * NB, r1 = k0 + NB;
+          if (k0 >= c1 || r1 >= o.np) continue;
+          T* x = kf(q) + static_cast<long>(r1) * o.ldk + k0;
+          GemmArgs<T> a = gemm_args<T>(x, o.ldk, o.np - r1, NB, T(1), T(0));
+          gemm_add_segment<T>(a, dinv(q) + static_cast<long>(k0) * NB, NB, x, o.ldk, NB);
+          g.push_back(a);
+        }
+        emit_gemm(P->factor, g, false);
+        for (int q = 0; q < P->nprob; ++q) {  // panel update
+          const auto& o = P->po[q];
+          const int c0 = pan * NB2;
+          if (c0 >= o.np) continue;
+          const int c1 = std::min(c0 + NB2, o.np), k0 = c0 + kk * NB, r1 = k0 + NB;
+          if (k0 >= c1 || r1 >= c1) continue;
+          GemmArgs<T> a = gemm_args<T>(kf(q) + static_cast<long>(r1) * o.ldk + k0, o.ldk, o.np - r1, NB, T(-1),
+                                       T(1));
+          gemm_add_segment<T>(a, kf(q) + static_cast<long>(k0) * o.ldk + r1, o.ldk,
+                              kf(q) + static_cast<long>(r1) * o.ldk + r1, o.ldk, c1 - r1);
+          g.push_back(a);
+        }
+        emit_gemm(P->factor, g, false);
+      }
+      rows_and_outer(P->factor, pan, true);
+    }
+  }
+
+  // panel rows right of the panel (block forward substitution) and the
+  // K = panel-width update below it; with_k = false updates Y only
+  void rows_and_outer(std::vector<rad_batch_plan::Launch>& out, int pan, bool with_k) {
+    std::vector<GemmArgs<T>> g;
+    for (int kk = 0; kk + 1 < NB2 / NB; ++kk) {
+      for (int q = 0; q < P->nprob; ++q) {
+        const auto& o = P->po[q];
+        const int c0 = pan * NB2;
+        if (c0 >= o.np) continue;
+        const int c1 = std::min(c0 + NB2, o.np), k0 = c0 + kk * NB, r1 = k0 + NB;
+        if (r1 >= c1) continue;
+        GemmArgs<T> a =
+            gemm_args<T>(kf(q) + static_cast<long>(r1) * o.ldk + k0, o.ldk, c1 - r1, NB, T(-1), T(1));
+        if (with_k && c1 < o.np)
+          gemm_add_segment<T>(a, kf(q) + static_cast<long>(k0) * o.ldk + c1, o.ldk,
+                              kf(q) + static_cast<long>(r1) * o.ldk + c1, o.ldk, o.np - c1);
+        gemm_add_segment<T>(a, y(q) + static_cast<long>(k0) * o.ldy, o.ldy, y(q) + static_cast<long>(r1) * o.ldy,
+                            o.ldy, o.n + 1);
+        g.push_back(a);
+      }
+      emit_gemm(out, g, false);
+    }
+    for (int q = 0; q < P->nprob; ++q) {
+      const auto& o = P->po[q];
+      const int c0 = pan * NB2;
+      if (c0 >= o.np) continue;
+      const int c1 = std::min(c0 + NB2, o.np);
+      if (c1 >= o.np) continue;
+      GemmArgs<T> a = gemm_args<T>(kf(q) + static_cast<long>(c1) * o.ldk + c0, o.ldk, o.np - c1, c1 - c0, T(-1),
+                                   T(1));
+      if (with_k)
+        gemm_add_segment<T>(a, kf(q) + static_cast<long>(c0) * o.ldk + c1, o.ldk,
+                            kf(q) + static_cast<long>(c1) * o.ldk + c1, o.ldk, o.np - c1);
+      gemm_add_segment<T>(a, y(q) + static_cast<long>(c0) * o.ldy, o.ldy, y(q) + static_cast<long>(c1) * o.ldy,
+                          o.ldy, o.n + 1);
+      g.push_back(a);
+    }
+    emit_gemm(out, g, false);
+  }
+
+  void forward_only() {
+    const int mp = max_panels();
+    for (int pan = 0; pan < mp; ++pan) rows_and_outer(P->fwd, pan, false);
+  }
+
+  // back substitution, each problem from its own last block down
+  void back() {
+    std::vector<GemmArgs<T>> g;
+    const int mp = max_panels();
+    for (int rp = 0; rp < mp; ++rp) {
+      for (int kr = 0; kr < NB2 / NB; ++kr) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = 0; q < P->nprob; ++q) {
+            const auto& o = P->po[q];
+            const int np2 = static_cast<int>(ceil_div(o.np, NB2));
+            const int pan = np2 - 1 - rp;
+            if (pan < 0) continue;
+            const int c0 = pan * NB2, c1 = std::min(c0 + NB2, o.np), k0 = c1 - NB * (kr + 1);
+            if (k0 < c0) continue;
+            if (pass == 0) {  // Y_k = D_k^{-1} Y_k
+              GemmArgs<T> a = gemm_args<T>(dinv(q) + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
+              gemm_add_segment<T>(a, y(q) + static_cast<long>(k0) * o.ldy, o.ldy, y(q) + static_cast<long>(k0) * o.ldy,
+                                  o.ldy, o.n + 1);
+              g.push_back(a);
+            } else if (k0 > c0) {  // rows of the panel above block k
+              GemmArgs<T> a = gemm_args<T>(kf(q) + static_cast<long>(c0) * o.ldk + k0, o.ldk, k0 - c0, NB, T(-1),
+                                           T(1));
+              gemm_add_segment<T>(a, y(q) + static_cast<long>(k0) * o.ldy, o.ldy, y(q) + static_cast<long>(c0) * o.ldy,
+                                  o.ldy, o.n + 1);
+              g.push_back(a);
+            }
+          }
+          emit_gemm(P->back, g, false);
+        }
+      }
+      for (int q = 0; q < P->nprob; ++q) {  // rows above the panel
+        const auto& o = P->po[q];
+        const int np2 = static_cast<int>(ceil_div(o.np, NB2));
+        const int pan = np2 - 1 - rp;
+        if (pan <= 0) continue;
+        const int c0 = pan * NB2, c1 = std::min(c0 + NB2, o.np);
+        GemmArgs<T> a = gemm_args<T>(kf(q) + c0, o.ldk, c0, c1 - c0, T(-1), T(1));
+        gemm_add_segment<T>(a, y(q) + static_cast<long>(c0) * o.ldy, o.ldy, y(q), o.ldy, o.n + 1);
+        g.push_back(a);
+      }
+      emit_gemm(P->back, g, false);
+    }
+  }
+
+  void residual() {
+    std::vector<GemmArgs<double>> g;
+    for (int q = 0; q < P->nprob; ++q) {
+      const auto& o = P->po[q];
+      double* p = reinterpret_cast<double*>(base + o.p);
+      double* x = reinterpret_cast<double*>(base + o.x);
+      double* r = reinterpret_cast<double*>(base + o.r);
+      GemmArgs<double> a = gemm_args<double>(p, o.ldp, o.n, static_cast<int>(ceil_div(o.n, 32) * 32), 1.0, 1.0);
+      gemm_add_segment<double>(a, x, o.ldx, r, o.ldx, o.n + 1);
+      g.push_back(a);
+    }
+    std::vector<int> ts(g.size() + 1, 0);
+    double flops = 0.0;
+    for (size_t k = 0; k < g.size(); ++k) {
+      ts[k + 1] = ts[k] + gemm_tiles<double>(g[k]);
+      flops += 2.0 * g[k].M * g[k].N[0] * g[k].K;
+    }
+    rad_batch_plan::Launch L{};
+    L.flops = flops;
+    L.kind = L_GEMM;
+    L.count = static_cast<int>(g.size());
+    L.off = tb->add(g.data(), g.size());
+    L.off2 = tb->add(ts.data(), ts.size());
+    L.grid = static_cast<unsigned>(std::min<int>(ts.back(), PERSISTENT_GRID));
+    P->resid.push_back(L);
+  }
+};
+
+size_t elem(int prec) { return prec == RAD_PREC_FP64 ? 8 : 4; }
+
+// buffer layout of the workspace (tables come last, see build_tables)
+void layout(rad_batch_plan* P) {
+  size_t used = 0;
+  auto take = [&](size_t bytes) {
+    const size_t off = align_up(used, 256);
+    used = off + align_up(bytes, 256);
+    return off;
+  };
+  P->io.clear();
+  P->po.clear();
+  for (int i = 0; i < P->count; ++i) {
+    const size_t n = static_cast<size_t>(P->inst[i].n);
+    rad_batch_plan::InstOff o{};
+    o.t = static_cast<int>(ceil_div(static_cast<int64_t>(n), 64));
+    o.pairs = static_cast<long>(o.t) * (o.t + 1) / 2;
+    o.ctrl = take(sizeof(EnfCtrl));
+    o.scale = take(n * sizeof(double));
+    o.inv_area = take(n * sizeof(double));
+    o.blkmax = take(2 * static_cast<size_t>(o.pairs) * sizeof(double));
+    o.partial = take(static_cast<size_t>(o.t + 1) * n * sizeof(double));
+    P->io.push_back(o);
+  }
+  const size_t es = elem(P->precision);
+  for (int i = 0; i < P->count; ++i) {
+    for (int b = 0; b < P->inst[i].bands; ++b) {
+      rad_batch_plan::ProbOff o{};
+      o.inst = i;
+      o.band = b;
+      o.n = static_cast<int>(P->inst[i].n);
+      o.np = static_cast<int>(ceil_div(o.n, NB) * NB);
+      o.ldk = static_cast<long>(o.np + 128 / es);
+      o.ldy = rhs_ld(o.n, static_cast<long>(128 / es));
+      o.ldx = rhs_ld(o.n, pad_elems<double>());
+      o.ldp = static_cast<long>(o.np + pad_elems<double>());
+      o.kf = take(static_cast<size_t>(o.np) * o.ldk * es);
+      o.dinv = take(static_cast<size_t>(o.np / NB) * NB * NB * es);
+      o.y = take(static_cast<size_t>(o.np) * o.ldy * es);
+      o.sc = take(sizeof(Scalars));
+      if (P->precision == RAD_PREC_FP32_IR) {
+        o.x = take(static_cast<size_t>(o.np) * o.ldx * 8);
+        o.r = take(static_cast<size_t>(o.np) * o.ldx * 8);
+        o.p = take(static_cast<size_t>(o.np) * o.ldp * 8);
+      }
+      P->po.push_back(o);
+    }
+  }
+  P->nprob = static_cast<int>(P->po.size());
+  P->tables_off = align_up(used, 256);
+}
+
+// descriptor tables and schedule for a workspace at `base` (may be null to size them)
+void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
+  P->factor.clear();
+  P->sweep_bytes = 0.0;
+  P->back.clear();
+  P->fwd.clear();
+  P->resid.clear();
+  // enforcement instances
+  std::vector<EnfInst> ei;
+  std::vector<long> pair_start(1, 0), fblk_start(1, 0), row_start(1, 0);
+  for (int i = 0; i < P->count; ++i) {
+    const rad_instance& s = P->inst[i];
+    const auto& o = P->io[i];
+    EnfInst e{};
+    e.F = s.F;
+    e.ldf = static_cast<long>(s.ldf);
+    e.n = static_cast<int>(s.n);
+    e.t = o.t;
+    e.pairs = o.pairs;
+    e.area = s.area;
+    e.inv_area = reinterpret_cast<double*>(base + o.inv_area);
+    e.nrays = s.n_rays;
+    e.mode = P->kappa;
+    e.scale = reinterpret_cast<double*>(base + o.scale);
+    e.partial = reinterpret_cast<double*>(base + o.partial);
+    e.blkmax = reinterpret_cast<double*>(base + o.blkmax);
+    e.ctrl = reinterpret_cast<EnfCtrl*>(base + o.ctrl);
+    ei.push_back(e);
+    pair_start.push_back(pair_start.back() + o.pairs);
+    fblk_start.push_back(fblk_start.back() + ceil_div(s.n, 256));
+    row_start.push_back(row_start.back() + s.n);
+    P->sweep_bytes += 16.0 * static_cast<double>(s.n) * (s.n + 1);
+  }
+  P->total_pairs = pair_start.back();
+  P->total_fblk = fblk_start.back();
+  P->total_rows = row_start.back();
+  P->off_enf = tb.add(ei.data(), ei.size());
+  P->off_pair = tb.add(pair_start.data(), pair_start.size());
+  P->off_fblk = tb.add(fblk_start.data(), fblk_start.size());
+  P->off_row = tb.add(row_start.data(), row_start.size());
+  // solve problems
+  std::vector<ProbDesc> pd;
+  std::vector<long> nprow(1, 0), nrow(1, 0);
+  for (int q = 0; q < P->nprob; ++q) {
+    const auto& o = P->po[q];
+    const rad_instance& s = P->inst[o.inst];
+    ProbDesc d{};
+    d.F = s.F;
+    d.ldf = static_cast<long>(s.ldf);
+    d.n = o.n;
+    d.np = o.np;
+    d.eps = s.eps[o.band];
+    d.rho = s.rho[o.band];
+    d.B = s.B[o.band];
+    d.ldb = static_cast<long>(s.ldb[o.band]);
+    d.kf = base + o.kf;
+    d.ldk = o.ldk;
+    d.dinv = base + o.dinv;
+    d.y = base + o.y;
+    d.ldy = o.ldy;
+    d.x = reinterpret_cast<double*>(base + o.x);
+    d.r = reinterpret_cast<double*>(base + o.r);
+    d.ldx = o.ldx;
+    d.p = reinterpret_cast<double*>(base + o.p);
+    d.ldp = o.ldp;
+    d.sc = reinterpret_cast<Scalars*>(base + o.sc);
+    pd.push_back(d);
+    nprow.push_back(nprow.back() + o.np);
+    nrow.push_back(nrow.back() + o.n);
+  }
+  P->total_nprow = nprow.back();
+  P->total_nrow = nrow.back();
+  P->off_pd = tb.add(pd.data(), pd.size());
+  P->off_nprow = tb.add(nprow.data(), nprow.size());
+  P->off_nrow = tb.add(nrow.data(), nrow.size());
+  if (P->precision == RAD_PREC_FP64) {
+    Sched<double> sch{P, base, &tb};
+    sch.factor();
+    sch.back();
+  } else {
+    Sched<float> sch{P, base, &tb};
+    sch.factor();
+    sch.back();
+    sch.forward_only();
+    sch.residual();
+  }
+}
+
+template <class T>
+hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const char* tables, hipStream_t s) {
+  for (const auto& L : ls) {
+    if (L.kind == L_GJ) {
+      ProfScope prof(s, RAD_PROF_DIAG_INVERSE, 2.0 * NB * NB * NB * L.count, 0.0);
+      hipLaunchKernelGGL(gj_batched<T>, dim3(L.grid), dim3(GJ_THREADS), 0, s,
+                         reinterpret_cast<const GjJob<T>*>(tables + L.off));
+    } else {
+      ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32, L.flops, 0.0);
+      const GemmArgs<T>* a = reinterpret_cast<const GemmArgs<T>*>(tables + L.off);
+      const int* ts = reinterpret_cast<const int*>(tables + L.off2);
+      if (L.trans)
+        hipLaunchKernelGGL((gemm_grouped_persistent<T, true>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
+      else
+        hipLaunchKernelGGL((gemm_grouped_persistent<T, false>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace rad
+
+using namespace rad;
+
+extern "C" int32_t rad_batch_plan_create(const rad_instance* inst, int32_t count, int32_t precision,
+                                         int32_t kappa_mode, rad_batch_plan** plan, size_t* work_bytes) {
+  clear_error();
+  RAD_REQUIRE(plan && work_bytes, RAD_EINVAL, "rad_batch_plan_create: NULL output");
+  *plan = nullptr;
+  RAD_REQUIRE(inst && count >= 1 && count <= (1 << 16), RAD_EINVAL, "rad_batch_plan_create: bad instance list");
+  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP32_IR, RAD_EINVAL,
+              "rad_batch_plan_create: unknown precision");
+  RAD_REQUIRE(kappa_mode == RAD_KAPPA_FRACVAR || kappa_mode == RAD_KAPPA_HALF, RAD_EINVAL,
+              "rad_batch_plan_create: unknown kappa_mode");
+  for (int i = 0; i < count; ++i) {
+    const rad_instance& s = inst[i];
+    RAD_REQUIRE(s.n >= 1 && s.n <= (1 << 20) && s.ldf >= s.n + 1 && s.F && s.area, RAD_EINVAL,
+                "rad_batch_plan_create: instance with bad n, ldf, F or area");
+    RAD_REQUIRE(kappa_mode == RAD_KAPPA_HALF || s.n_rays, RAD_EINVAL,
+                "rad_batch_plan_create: n_rays required for RAD_KAPPA_FRACVAR");
+    RAD_REQUIRE(s.bands == 1 || s.bands == 2, RAD_EINVAL, "rad_batch_plan_create: bands must be 1 or 2");
+    for (int b = 0; b < s.bands; ++b)
+      RAD_REQUIRE(s.eps[b] && s.rho[b] && s.B[b] && s.ldb[b] >= s.n + 1, RAD_EINVAL,
+                  "rad_batch_plan_create: band with NULL eps/rho/B or ldb < n+1");
+  }
+  rad_batch_plan* P = new rad_batch_plan();
+  P->count = count;
+  P->precision = precision;
+  P->kappa = kappa_mode;
+  P->inst.assign(inst, inst + count);
+  layout(P);
+  TableBuilder tb;
+  // table sizes do not depend on the workspace address; size them at a dummy one
+  build_tables(P, reinterpret_cast<char*>(static_cast<uintptr_t>(1) << 24), tb);
+  P->work_bytes = P->tables_off + align_up(tb.data.size(), 256);
+  *plan = P;
+  *work_bytes = P->work_bytes;
+  return RAD_OK;
+}
+
+extern "C" void rad_batch_plan_destroy(rad_batch_plan* plan) { delete plan; }
+
+extern "C" int32_t rad_batch_prepare(rad_batch_plan* P, void* work, size_t work_bytes, void* stream) {
+  clear_error();
+  RAD_REQUIRE(P, RAD_EINVAL, "rad_batch_prepare: NULL plan");
+  RAD_REQUIRE(work && work_bytes >= P->work_bytes && reinterpret_cast<uintptr_t>(work) % 256 == 0,
+              RAD_EWORKSPACE, "rad_batch_prepare: workspace too small or not 256-byte aligned");
+  TableBuilder tb;
+  build_tables(P, static_cast<char*>(work), tb);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RAD_HIP_CHECK(hipMemcpyAsync(static_cast<char*>(work) + P->tables_off, tb.data.data(), tb.data.size(),
+                               hipMemcpyHostToDevice, s));
+  RAD_HIP_CHECK(hipStreamSynchronize(s));
+  P->prepared_for = work;
+  return RAD_OK;
+}
+
+extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enforce_tol, int32_t enforce_iters,
+                                 int32_t ir_steps, void* stream) {
+  clear_error();
+  RAD_REQUIRE(P && work, RAD_EINVAL, "rad_batch_run: NULL plan or workspace");
+  RAD_REQUIRE(P->prepared_for == work, RAD_EINVAL, "rad_batch_run: workspace was not prepared with this plan");
+  RAD_REQUIRE(enforce_iters >= 0 && ir_steps >= 0 && enforce_tol >= 0.0, RAD_EINVAL,
+              "rad_batch_run: negative iteration count or tolerance");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const char* tables = static_cast<const char*>(work) + P->tables_off;
+  const EnfInst* ei = reinterpret_cast<const EnfInst*>(tables + P->off_enf);
+  const long* pair_start = reinterpret_cast<const long*>(tables + P->off_pair);
+  const long* fblk_start = reinterpret_cast<const long*>(tables + P->off_fblk);
+  const long* row_start = reinterpret_cast<const long*>(tables + P->off_row);
+  const ProbDesc* pd = reinterpret_cast<const ProbDesc*>(tables + P->off_pd);
+  const long* nprow = reinterpret_cast<const long*>(tables + P->off_nprow);
+  const long* nrow = reinterpret_cast<const long*>(tables + P->off_nrow);
+  const int C = P->count, Q = P->nprob;
+  const unsigned cb = static_cast<unsigned>(ceil_div(C, 64)), qb = static_cast<unsigned>(ceil_div(Q, 64));
+  // ---- enforcement of every instance (fixed launches, device-side stop)
+  hipLaunchKernelGGL(enf_init_batched, dim3(cb), dim3(64), 0, s, ei, C);
+  if (enforce_iters > 0) {
+    hipLaunchKernelGGL(enf_inv_area_batched, dim3(static_cast<unsigned>(P->total_fblk)), dim3(256), 0, s, ei,
+                       fblk_start, C);
+    for (int it = 0; it < enforce_iters; ++it) {
+      const int parity = it & 1;
+      {
+        ProfScope prof(s, RAD_PROF_ENFORCE_SWEEP, 0.0, P->sweep_bytes);
+        hipLaunchKernelGGL(enf_sweep_batched, dim3(static_cast<unsigned>(P->total_pairs)), dim3(ENF_THREADS), 0, s,
+                           ei, pair_start, C, it == 0 ? 1 : 0);
+      }
+      hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fblk)), dim3(256), 0, s, ei,
+                         fblk_start, C, parity);
+      hipLaunchKernelGGL(enf_decide_batched, dim3(cb), dim3(64), 0, s, ei, C, parity, enforce_tol);
+    }
+    hipLaunchKernelGGL(enf_apply_scale_batched, dim3(static_cast<unsigned>(P->total_rows)), dim3(256), 0, s, ei,
+                       row_start, C);
+  }
+  // ---- Gebhart solves of every (instance, band)
+  hipLaunchKernelGGL(b_scalars_init, dim3(qb), dim3(64), 0, s, pd, Q, 1);
+  const unsigned npr = static_cast<unsigned>(P->total_nprow), nr = static_cast<unsigned>(P->total_nrow);
+  if (P->precision == RAD_PREC_FP64) {
+    hipLaunchKernelGGL(b_form<double>, dim3(npr), dim3(256), 0, s, pd, nprow, Q);
+    RAD_HIP_CHECK(run_launches<double>(P->factor, tables, s));
+    RAD_HIP_CHECK(run_launches<double>(P->back, tables, s));
+    hipLaunchKernelGGL(b_copy<double>, dim3(nr), dim3(256), 0, s, pd, nrow, Q, 0);
+  } else {
+    hipLaunchKernelGGL(b_form<float>, dim3(npr), dim3(256), 0, s, pd, nprow, Q);
+    RAD_HIP_CHECK(run_launches<float>(P->factor, tables, s));
+    RAD_HIP_CHECK(run_launches<float>(P->back, tables, s));
+    if (ir_steps == 0) {
+      hipLaunchKernelGGL(b_copy<float>, dim3(nr), dim3(256), 0, s, pd, nrow, Q, 0);
+    } else {
+      hipLaunchKernelGGL(b_zero_xr, dim3(npr), dim3(256), 0, s, pd, nprow, Q);
+      hipLaunchKernelGGL(b_form_p64, dim3(npr), dim3(256), 0, s, pd, nprow, Q);
+      hipLaunchKernelGGL(b_copy<float>, dim3(nr), dim3(256), 0, s, pd, nrow, Q, 1);
+      for (int st = 0; st < ir_steps; ++st) {
+        hipLaunchKernelGGL(b_scalars_init, dim3(qb), dim3(64), 0, s, pd, Q, 0);
+        hipLaunchKernelGGL(b_residual_init, dim3(nr), dim3(256), 0, s, pd, nrow, Q);
+        RAD_HIP_CHECK(run_launches<double>(P->resid, tables, s));
+        hipLaunchKernelGGL(b_residual_to_rhs, dim3(nr), dim3(256), 0, s, pd, nrow, Q);
+        RAD_HIP_CHECK(run_launches<float>(P->fwd, tables, s));
+        RAD_HIP_CHECK(run_launches<float>(P->back, tables, s));
+        hipLaunchKernelGGL(b_apply_correction, dim3(nr), dim3(256), 0, s, pd, nrow, Q);
+      }
+      hipLaunchKernelGGL(b_copy<float>, dim3(nr), dim3(256), 0, s, pd, nrow, Q, 2);
+    }
+  }
+  RAD_HIP_CHECK(hipGetLastError());
+  return RAD_OK;
+}
+
+extern "C" int32_t rad_batch_stats(const rad_batch_plan* P, const void* work, rad_stats* out, void* stream) {
+  clear_error();
+  RAD_REQUIRE(P && work && out, RAD_EINVAL, "rad_batch_stats: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const char* base = static_cast<const char*>(work);
+  std::vector<EnfCtrl> ec(P->count);
+  std::vector<Scalars> sc(P->nprob);
+  for (int i = 0; i < P->count; ++i)
+    RAD_HIP_CHECK(hipMemcpyAsync(&ec[i], base + P->io[i].ctrl, sizeof(EnfCtrl), hipMemcpyDeviceToHost, s));
+  for (int q = 0; q < P->nprob; ++q)
+    RAD_HIP_CHECK(hipMemcpyAsync(&sc[q], base + P->po[q].sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  RAD_HIP_CHECK(hipStreamSynchronize(s));
+  int32_t worst = RAD_OK;
+  for (int i = 0; i < P->count; ++i) {
+    rad_stats& o = out[i];
+    o = rad_stats{};
+    o.iters = ec[i].iters;
+    o.converged = ec[i].converged;
+    o.closure_defect = ec[i].last_defect;
+    o.recip_err = ec[i].last_recip;
+    o.device_status = ec[i].status;
+  }
+  for (int q = 0; q < P->nprob; ++q) {
+    rad_stats& o = out[P->po[q].inst];
+    o.device_status = std::min(o.device_status, sc[q].status);
+    o.ir_correction = std::max(o.ir_correction, sc[q].max_d);
+    o.ir_residual = std::max(o.ir_residual, sc[q].max_r);
+  }
+  for (int i = 0; i < P->count; ++i) worst = std::min(worst, out[i].device_status);
+  if (worst < 0) set_error("rad_batch_stats: an instance reported a device-side error (see device_status)");
+  return worst;
+}

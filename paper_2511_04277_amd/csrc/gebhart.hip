@@ -32,400 +32,10 @@
 // U^T (diagonal blocks D_k^{-T}) followed by a block backward solve with L^T,
 // both reusing the stored factors through transposed-A GEMMs; in FP32_IR mode
 // the residual G - K^T Lambda = (G - Lambda) + P^T Lambda is formed in FP64.
-#include "common.h"
-#include "gemm.h"
-
-#include <algorithm>
-#include <cmath>
+#include "gebhart_kernels.h"
 
 namespace rad {
 namespace {
-
-constexpr int NB = 128;          // diagonal block (Gauss-Jordan inverse)
-constexpr int NB2 = 1024;        // panel width of the two-level updates
-
-template <class T>
-constexpr long pad_elems() { return 128 / static_cast<long>(sizeof(T)); }
-
-// ---------------------------------------------------------------- layout ----
-struct FactorLayout {
-  int64_t n, np, P;
-  long ldk;
-  size_t kf_off, dinv_off, bytes;
-};
-
-template <class T>
-FactorLayout factor_layout(int64_t n) {
-  FactorLayout f;
-  f.n = n;
-  f.np = ceil_div(n, NB) * NB;
-  f.P = f.np / NB;
-  f.ldk = static_cast<long>(f.np + pad_elems<T>());
-  f.kf_off = 0;
-  f.dinv_off = align_up(static_cast<size_t>(f.np) * f.ldk * sizeof(T), 256);
-  f.bytes = f.dinv_off + align_up(static_cast<size_t>(f.P) * NB * NB * sizeof(T), 256);
-  return f;
-}
-
-// right-hand-side buffers: columns padded to a multiple of 128 plus 128 bytes
-inline long rhs_ld(int64_t n, long pad) { return static_cast<long>(ceil_div(n + 1, 128) * 128 + pad); }
-
-struct Scalars {
-  int status;
-  int pad;
-  double max_r;      // max |residual|
-  double max_d;      // max |correction|
-  double red[2];     // REF check outputs
-};
-
-template <class T>
-struct Fact {
-  T* kf;
-  long ldk;
-  T* dinv;
-  int n, np, P;
-};
-
-template <class T>
-Fact<T> make_fact(void* base, const FactorLayout& l) {
-  Fact<T> f;
-  f.kf = reinterpret_cast<T*>(static_cast<char*>(base) + l.kf_off);
-  f.ldk = l.ldk;
-  f.dinv = reinterpret_cast<T*>(static_cast<char*>(base) + l.dinv_off);
-  f.n = static_cast<int>(l.n);
-  f.np = static_cast<int>(l.np);
-  f.P = static_cast<int>(l.P);
-  return f;
-}
-
-// ---------------------------------------------------------------- kernels ---
-__global__ void scalars_init(Scalars* sc) {
-  if (threadIdx.x == 0) {
-    sc->status = 0;
-    sc->max_r = 0.0;
-    sc->max_d = 0.0;
-    sc->red[0] = sc->red[1] = 0.0;
-  }
-}
-
-__global__ void scalars_init_partial(Scalars* sc) {
-  if (threadIdx.x == 0) {
-    sc->max_r = 0.0;
-    sc->max_d = 0.0;
-  }
-}
-
-__global__ void check_optical(const double* __restrict__ eps, const double* __restrict__ rho,
-                              int n, Scalars* sc) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double e = eps ? eps[i] : 0.5, r = rho[i];
-  if (!(e >= 0.0 && e <= 1.0 && r >= 0.0 && r <= 1.0)) raise_status(&sc->status, RAD_ENONFINITE);
-}
-
-// K (padded with identity) and E (padded with zeros) in precision T.
-// Row i of both, one workgroup per row of the padded size.
-template <class T>
-__global__ void __launch_bounds__(256)
-geb_form(const double* __restrict__ F, long ldf, int n, const double* __restrict__ eps,
-         const double* __restrict__ rho, T* __restrict__ KF, long ldk, int np,
-         T* __restrict__ Y, long ldy, Scalars* sc) {
-  const int i = blockIdx.x;
-  const double* frow = F + static_cast<long>(i) * ldf;
-  T* krow = KF + static_cast<long>(i) * ldk;
-  T* yrow = Y + static_cast<long>(i) * ldy;
-  int bad = 0;
-  const long jend = ldk > ldy ? ldk : ldy;
-  for (long j = threadIdx.x; j < jend; j += blockDim.x) {
-    double kv = (i == j) ? 1.0 : 0.0;
-    double yv = 0.0;
-    if (i < n && j <= n) {
-      double f = frow[j];
-      bad |= !(f >= 0.0 && f <= 1.0e300);
-      if (j < n) {
-        kv = kv - f * rho[j];
-        yv = f * eps[j];
-      } else {
-        yv = f;  // space column: no emissivity factor (eq. B.6)
-      }
-    }
-    if (j < ldk) krow[j] = (j < np) ? static_cast<T>(kv) : T(0);
-    if (j < ldy) yrow[j] = static_cast<T>(yv);
-  }
-  if (bad) raise_status(&sc->status, RAD_ENONFINITE);
-}
-
-// P = F_sq diag(rho) in FP64, zero outside n x n (refinement residuals).
-__global__ void __launch_bounds__(256)
-form_p64(const double* __restrict__ F, long ldf, int n, const double* __restrict__ rho,
-         double* __restrict__ P, long ldp) {
-  const int i = blockIdx.x;
-  for (long j = threadIdx.x; j < ldp; j += blockDim.x)
-    P[static_cast<long>(i) * ldp + j] = (i < n && j < n) ? F[static_cast<long>(i) * ldf + j] * rho[j] : 0.0;
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) {
-  for (long q = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; q < count;
-       q += static_cast<long>(gridDim.x) * blockDim.x)
-    p[q] = T(0);
-}
-
-// Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting.  Thread t
-// keeps column j = t % NB of the 16 contiguous rows g*16 .. g*16+15
-// (g = t / NB) in registers.  Step p is one uniform update
-//   m_ij <- m_ij - c_i r_j,   r_j = m_pj d (j != p), r_p = d = 1 / m_pp,
-//                             c_i = m_ip (i != p),   c_p = -1,
-// after row p and column p have been published through LDS and zeroed in
-// registers: that yields the new row p (r), column p (-c d) and pivot (d) of
-// the in-place inverse with one FMA per element.  Pivots are taken in the
-// order p = g*16 + q (q outer), which keeps register indices static; any
-// order of diagonal pivots gives the same inverse and diagonal dominance
-// makes every order stable.  LDS is double-buffered, one barrier per step.
-constexpr int GJ_THREADS = 1024;
-
-// 1/x: hardware reciprocal refined by Newton steps to full precision
-__device__ __forceinline__ double recip_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * (2.0 - x * r);
-  r = r * (2.0 - x * r);
-  return r;
-}
-__device__ __forceinline__ float recip_nr(float x) {
-  float r = __builtin_amdgcn_rcpf(x);
-  return r * (2.0f - x * r);
-}
-
-template <class T>
-__global__ void __launch_bounds__(GJ_THREADS)
-gj_inverse(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
-  constexpr int G = GJ_THREADS / NB;  // 8 row groups
-  constexpr int R = NB / G;           // 16 rows per thread
-  __shared__ T sRow[2][NB];
-  __shared__ __attribute__((aligned(16))) T sCol[2][NB];
-  const int tid = threadIdx.x;
-  const int j = tid & (NB - 1);
-  const int g = tid / NB;
-  T m[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) m[q] = A[static_cast<long>(g * R + q) * lda + j];
-  const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
-  int singular = 0;
-#pragma unroll
-  for (int q0 = 0; q0 < R; ++q0) {
-#pragma unroll 1
-    for (int gg = 0; gg < G; ++gg) {
-      const int p = gg * R + q0;
-      const int buf = gg & 1;  // alternates every step (G is even)
-      if (g == gg) {  // owner of row p publishes it and clears it
-        sRow[buf][j] = m[q0];
-        m[q0] = T(0);
-      }
-      if (j == p) {   // owner of column p publishes it (c_p = -1) and clears it
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          sCol[buf][g * R + q] = (g == gg && q == q0) ? T(-1) : m[q];
-          m[q] = T(0);
-        }
-      }
-      __syncthreads();
-      const T piv = sRow[buf][p];
-      T d = recip_nr(piv);
-      // K has unit diagonal scale and its pivots stay >= 1 - max rho for
-      // valid input; a pivot below this threshold means a singular K.
-      if (!(fabs(static_cast<double>(piv)) > tiny) || !(fabs(static_cast<double>(d)) < 1e300)) {
-        singular = 1;
-        d = T(0);
-      }
-      const T rj = (j == p) ? d : sRow[buf][j] * d;
-      const T* col = &sCol[buf][g * R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) m[q] = m[q] - col[q] * rj;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) out[(g * R + q) * NB + j] = m[q];
-  if (singular && tid == 0) raise_status(&sc->status, RAD_ESINGULAR);
-}
-
-// dst (D, rows < n, cols <= n) <- src (S)
-template <class S, class D>
-__global__ void __launch_bounds__(256)
-copy_block(const S* __restrict__ src, long lds, int n, D* __restrict__ dst, long ldd) {
-  const int i = blockIdx.x;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    dst[static_cast<long>(i) * ldd + j] = static_cast<D>(src[static_cast<long>(i) * lds + j]);
-}
-
-__device__ inline void block_max(double v, double* target) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(target, v);
-}
-
-// R = E - X  (rows < n, cols <= n), E from F and eps on the fly
-__global__ void __launch_bounds__(256)
-residual_init(const double* __restrict__ F, long ldf, int n, const double* __restrict__ eps,
-              const double* __restrict__ X, long ldx, double* __restrict__ R, long ldr) {
-  const int i = blockIdx.x;
-  const double* f = F + static_cast<long>(i) * ldf;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
-    double e = (j < n) ? f[j] * eps[j] : f[n];
-    R[static_cast<long>(i) * ldr + j] = e - X[static_cast<long>(i) * ldx + j];
-  }
-}
-
-// R = G - L  (rows < n, cols <= n)
-__global__ void __launch_bounds__(256)
-adj_residual_init(const double* __restrict__ G, long ldg, int n, const double* __restrict__ L, long ldl,
-                  double* __restrict__ R, long ldr) {
-  const int i = blockIdx.x;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    R[static_cast<long>(i) * ldr + j] = G[static_cast<long>(i) * ldg + j] - L[static_cast<long>(i) * ldl + j];
-}
-
-// Y32 <- R (rows < n, cols <= n), records max |R|
-__global__ void __launch_bounds__(256)
-residual_to_rhs(const double* __restrict__ R, long ldr, int n, float* __restrict__ Y, long ldy,
-                Scalars* sc) {
-  const int i = blockIdx.x;
-  double m = 0.0;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
-    double v = R[static_cast<long>(i) * ldr + j];
-    m = fmax(m, fabs(v));
-    Y[static_cast<long>(i) * ldy + j] = static_cast<float>(v);
-  }
-  block_max(m, &sc->max_r);
-}
-
-// X += Y32 (rows < n, cols <= n), records max |delta|
-__global__ void __launch_bounds__(256)
-apply_correction(const float* __restrict__ Y, long ldy, int n, double* __restrict__ X, long ldx,
-                 Scalars* sc) {
-  const int i = blockIdx.x;
-  double m = 0.0;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
-    double d = static_cast<double>(Y[static_cast<long>(i) * ldy + j]);
-    m = fmax(m, fabs(d));
-    X[static_cast<long>(i) * ldx + j] += d;
-  }
-  block_max(m, &sc->max_d);
-}
-
-// Y (T, np rows x ldy, zero outside n x (n+1)) <- G (fp64)
-template <class T>
-__global__ void __launch_bounds__(256)
-load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long ldy) {
-  const int i = blockIdx.x;
-  T* y = Y + static_cast<long>(i) * ldy;
-  for (long j = threadIdx.x; j < ldy; j += blockDim.x)
-    y[j] = (j <= n && i < n) ? static_cast<T>(G[static_cast<long>(i) * ldg + j]) : T(0);
-}
-
-// REF closure residual: one wave per row, fixed-order reduction.
-__global__ void __launch_bounds__(256)
-ref_closure(const double* __restrict__ B, long ldb, int n, Scalars* sc) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
-  double s = 0.0;
-  if (row < n)
-    for (int j = l; j <= n; j += 64) s += B[static_cast<long>(row) * ldb + j];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  double d = (row < n) ? fabs(s - 1.0) : 0.0;
-  if (l == 0) atomic_max_nonneg(&sc->red[0], d);
-}
-
-// REF reciprocity residual max |eps_i A_i B_ij - eps_j A_j B_ji| over 64x64 tile pairs
-__global__ void __launch_bounds__(256)
-ref_reciprocity(const double* __restrict__ B, long ldb, int n, const double* __restrict__ eps,
-                const double* __restrict__ area, Scalars* sc) {
-  __shared__ double sT[64][65];
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (J < I) return;
-  const int tid = threadIdx.x, c = tid & 63, rg = tid >> 6;
-  for (int m = 0; m < 16; ++m) {
-    int r = rg + 4 * m;
-    int i = J * 64 + r, j = I * 64 + c;
-    sT[r][c] = (i < n && j < n) ? eps[i] * area[i] * B[static_cast<long>(i) * ldb + j] : 0.0;
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int m = 0; m < 16; ++m) {
-    int r = rg + 4 * m;
-    int i = I * 64 + r, j = J * 64 + c;
-    if (i < n && j < n) {
-      double g = eps[i] * area[i] * B[static_cast<long>(i) * ldb + j];
-      mx = fmax(mx, fabs(g - sT[c][r]));
-    }
-  }
-  block_max(mx, &sc->red[1]);
-}
-
-__global__ void copy_scalars_out(const Scalars* sc, double* out) {
-  if (threadIdx.x == 0) {
-    out[0] = sc->red[0];
-    out[1] = sc->red[1];
-  }
-}
-
-// grad_eps[k] = sum_i Lambda_ik F_ik: partial sums over row chunks of 128,
-// then a fixed-order sum of the partials (reproducible).
-constexpr int GE_ROWS = 128;
-__global__ void __launch_bounds__(256)
-adj_grad_eps_partial(const double* __restrict__ L, long ldl, const double* __restrict__ F, long ldf,
-                     int n, double* __restrict__ part) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (k >= n) return;
-  const int i0 = c * GE_ROWS, i1 = min(n, i0 + GE_ROWS);
-  double s = 0.0;
-  for (int i = i0; i < i1; ++i) s += L[static_cast<long>(i) * ldl + k] * F[static_cast<long>(i) * ldf + k];
-  part[static_cast<long>(c) * n + k] = s;
-}
-
-__global__ void __launch_bounds__(256)
-adj_grad_eps_final(const double* __restrict__ part, int n, int chunks, double* __restrict__ ge) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[static_cast<long>(c) * n + k];
-  ge[k] = s;
-}
-
-// grad_rho[k] = (1/rho_k) sum_j B_kj (Lambda_kj - G_kj)   (one wave per row)
-__global__ void __launch_bounds__(256)
-adj_grad_rho(const double* __restrict__ L, long ldl, const double* __restrict__ G, long ldg,
-             const double* __restrict__ B, long ldb, const double* __restrict__ rho, int n,
-             double* __restrict__ gr) {
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
-  if (k >= n) return;
-  double s = 0.0;
-  for (int j = l; j <= n; j += 64)
-    s += B[static_cast<long>(k) * ldb + j] *
-         (L[static_cast<long>(k) * ldl + j] - G[static_cast<long>(k) * ldg + j]);
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (l == 0 && rho[k] >= 1e-3) gr[k] = s / rho[k];
-}
-
-// direct form for small rho_k: sum_j B_kj sum_i F_ik Lambda_ij
-__global__ void __launch_bounds__(256)
-adj_grad_rho_direct(const double* __restrict__ L, long ldl, const double* __restrict__ F, long ldf,
-                    const double* __restrict__ B, long ldb, const double* __restrict__ rho, int n,
-                    double* __restrict__ gr) {
-  const int k = blockIdx.x;
-  if (rho[k] >= 1e-3) return;
-  __shared__ double red[4];
-  double acc = 0.0;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x) {
-    double t = 0.0;
-    for (int i = 0; i < n; ++i) t += F[static_cast<long>(i) * ldf + k] * L[static_cast<long>(i) * ldl + j];
-    acc += B[static_cast<long>(k) * ldb + j] * t;
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) gr[k] = red[0] + red[1] + red[2] + red[3];
-}
 
 // ---------------------------------------------------------------- drivers ---
 #define RAD_GEMM(args, trans)                                  \

@@ -150,13 +150,15 @@ __device__ __forceinline__ void lds_stage_store(T (*sA)[GemmCfg<T>::KC + GemmCfg
   for (int q = 0; q < E; ++q) sB[k][nb + q] = rb[q];
 }
 
+// One 128 x 128 output tile: column-tile index bx (over both segments),
+// row-tile index by.
 template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
   __shared__ T sA[2][GEMM_TILE][KC + GemmCfg<T>::PA];
   __shared__ T sB[2][KC][GEMM_TILE + GemmCfg<T>::PB];
-  int ct = blockIdx.x;
+  int ct = bx;
   int seg = 0;
   if (ct >= g.ntile[0]) {
     seg = 1;
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
   const T* __restrict__ A = g.A;
   const long lda = g.lda;
   const int N = g.N[seg], M = g.M, K = g.K;
-  const int m0 = blockIdx.y * GEMM_TILE, n0 = ct * GEMM_TILE;
+  const int m0 = by * GEMM_TILE, n0 = ct * GEMM_TILE;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int li = l & 15, lg = l >> 4;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
@@ -206,6 +208,43 @@ __global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
     __syncthreads();
   }
   store_tile<T>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
+}
+
+template <class T, bool TRANS_A>
+__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
+  gemm_tile<T, TRANS_A>(g, blockIdx.x, blockIdx.y);
+}
+
+// Grouped launch: many independent products in one grid.  probs[p] covers
+// tiles [tile_start[p], tile_start[p+1]) in row-major tile order.
+template <class T, bool TRANS_A>
+__global__ void __launch_bounds__(256, 2)
+gemm_grouped(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {  // last p with tile_start[p] <= b
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const GemmArgs<T>& g = probs[lo];
+  const int local = b - tile_start[lo];
+  const int ntx = g.ntile[0] + g.ntile[1];
+  gemm_tile<T, TRANS_A>(g, local % ntx, local / ntx);
+}
+
+// Host: number of 128 x 128 tiles of a product (fills g.ntile).
+template <class T>
+inline int gemm_tiles(GemmArgs<T>& a) {
+  if (a.M <= 0 || a.K <= 0) {
+    a.ntile[0] = a.ntile[1] = 0;
+    return 0;
+  }
+  int total = 0;
+  for (int q = 0; q < 2; ++q) {
+    a.ntile[q] = (q < a.nseg && a.N[q] > 0) ? (a.N[q] + GEMM_TILE - 1) / GEMM_TILE : 0;
+    total += a.ntile[q];
+  }
+  return total * ((a.M + GEMM_TILE - 1) / GEMM_TILE);
 }
 
 // Host-side launcher: one or two column segments.
