@@ -47,13 +47,50 @@ def solve_flops(n: int) -> float:
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * (n + 1)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_lds_f64_open_box_n8192_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2511_04277_amd", "csrc", "gemm.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kname: str, prec: str):
+    """HBM bytes per launch of the GEMM from the committed counter summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE averages per dispatch,
+    scaled by the same counters on a plain copy of known size, together with
+    the hash of the kernel source they were taken on; a changed kernel gives
+    None (counters are stale).
+    """
+    if prec != "fp64" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or vals.get("kernel") != kname:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["auto", "fp64", "fp32_ir"], default="auto")
+    ap.add_argument("--precision", choices=["auto", "fp64", "fp32_ir1", "fp32_ir"], default="auto",
+                    help="Gebhart variant of the step (auto: the fastest within 1e-10 of the oracle)")
     ap.add_argument("--solve-reps", type=int, default=3)
+    ap.add_argument("--solve-variants", default="fp64,fp32_ir1,fp32_ir",
+                    help="comma list of Gebhart variants timed alone and checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -109,26 +146,42 @@ def main() -> int:
         f"reciprocity error {est['recip_err']:.2e}")
     F_enf_host = F.cpu().numpy()
 
-    # ---- Gebhart alone, both precisions ----------------------------------
+    # ---- plain copy of known size: scale for the HBM traffic counters -----
+    # (reads and writes n (n+1) doubles; a counter run divides the copy's
+    # FETCH_SIZE / WRITE_SIZE by these bytes to calibrate the GEMM's)
+    Fcal = torch.empty_like(F0)
+    torch.mul(F0, 1.0, out=Fcal)
+    torch.cuda.synchronize()
+    del Fcal
+
+    # ---- Gebhart alone: FP64, and FP32 + FP64 refinement ------------------
+    # FP32+IR with one refinement step (its error is measured against the
+    # oracle below) and refined until the correction is <= 1e-12
+    variants = {"fp64": ("fp64", 0.0, 0), "fp32_ir1": ("fp32_ir", 1.0, 1), "fp32_ir": ("fp32_ir", 1e-12, 4)}
+    chosen = [v for v in args.solve_variants.split(",") if v]
+    if args.precision != "auto" and args.precision not in chosen:
+        chosen.append(args.precision)
     solve = {}
     factors = {}
-    for prec in ("fp64", "fp32_ir"):
-        B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf)
-        factors[prec] = fac
+    for name in chosen:
+        prec_v, ir_tol, ir_max = variants[name]
+        B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec_v, ir_tol=ir_tol, ir_max=ir_max, out=Bbuf,
+                                     factors=factors.get(prec_v))
+        factors[prec_v] = fac
         torch.cuda.synchronize()
         times = []
         for _ in range(args.solve_reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf,
+            B, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec_v, ir_tol=ir_tol, ir_max=ir_max, out=Bbuf,
                                          factors=fac)
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
         ms = float(np.median(times))
-        solve[prec] = {"ms": ms, "ref_per_s": 1000.0 / ms, "ir_steps": st.get("ir_steps", 0),
-                       "B": B.cpu().numpy()}
-        log(f"gebhart {prec}: {ms:.2f} ms  ({1000.0 / ms:.2f} REF/s), stats {st}")
+        solve[name] = {"precision": prec_v, "ir_tol": ir_tol, "ir_max": ir_max, "ms": ms,
+                       "ref_per_s": 1000.0 / ms, "ir_steps": st.get("ir_steps", 0), "B": B.cpu().numpy()}
+        log(f"gebhart {name}: {ms:.2f} ms  ({1000.0 / ms:.2f} REF/s), stats {st}")
 
     # ---- oracle on the same enforced F: accuracy (and CPU baseline) -------
     cpu = None
@@ -136,18 +189,19 @@ def main() -> int:
     t_orc = time.perf_counter()
     b_ref = oracle.gebhart_ref(F_enf_host, inst.eps[0], inst.rho[0])
     t_orc_solve = time.perf_counter() - t_orc
-    for prec in solve:
-        solve[prec]["max_abs_err"] = float(np.abs(solve[prec].pop("B") - b_ref).max())
-        log(f"gebhart {prec}: max|B - B_oracle| = {solve[prec]['max_abs_err']:.3e}")
-    ok = [p for p in solve if solve[p]["max_abs_err"] <= ERR_BOUND]
+    for name in solve:
+        solve[name]["max_abs_err"] = float(np.abs(solve[name].pop("B") - b_ref).max())
+        log(f"gebhart {name}: max|B - B_oracle| = {solve[name]['max_abs_err']:.3e}")
+    ok = [v for v in solve if solve[v]["max_abs_err"] <= ERR_BOUND]
     if args.precision != "auto":
-        prec = args.precision
+        choice = args.precision
     else:
-        prec = min(ok or list(solve), key=lambda p: solve[p]["ms"])
-    for p in solve:
-        peak = PEAK_TFLOPS["fp64" if p == "fp64" else "fp32"]
-        solve[p]["solve_tflops"] = solve_flops(n) / (solve[p]["ms"] * 1e-3) / 1e12
-        solve[p]["lu_mfma_frac_of_peak"] = solve[p]["solve_tflops"] / peak
+        choice = min(ok or list(solve), key=lambda v: solve[v]["ms"])
+    for v in solve:
+        peak = PEAK_TFLOPS["fp64" if solve[v]["precision"] == "fp64" else "fp32"]
+        solve[v]["solve_tflops"] = solve_flops(n) / (solve[v]["ms"] * 1e-3) / 1e12
+        solve[v]["solve_frac_of_peak"] = solve[v]["solve_tflops"] / peak
+    prec, ir_tol, ir_max = variants[choice]
 
     # ---- the step ---------------------------------------------------------
     fac = factors[prec]
@@ -155,10 +209,10 @@ def main() -> int:
     def step():
         F.copy_(F0)
         rad.enforce_vf_(F, area, nrays, kappa="fracvar", tol=ENF_TOL, max_iter=ENF_MAX, want_stats=False)
-        B, _, _ = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=1e-12, ir_max=4, out=Bbuf,
+        B, _, _ = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=ir_tol, ir_max=ir_max, out=Bbuf,
                                   factors=fac, want_stats=False)
         chk = rad.ref_check(B, eps, area)
-        ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, F, rho, B, G, ir_tol=1e-12, ir_max=4, want_stats=False)
+        ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, F, rho, B, G, ir_tol=ir_tol, ir_max=ir_max, want_stats=False)
         y1, w1 = rad.aggregate_nodes(B, w_ref, grp1, n1, out=Y1, validate=False)
         y2, _ = rad.aggregate_nodes(y1, w1, grp2, n2, out=Y2, validate=False)
         return chk, ge, gr, y2
@@ -167,7 +221,8 @@ def main() -> int:
         step()
     torch.cuda.synchronize()
     lib.rad_profile_enable(1)
-    lib.rad_profile_read((L.RadKernelProfile * 5)(), 5)
+    NK = len(L.PROFILE_KINDS)
+    lib.rad_profile_read((L.RadKernelProfile * NK)(), NK)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -176,8 +231,8 @@ def main() -> int:
     e1.record()
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    profs = (L.RadKernelProfile * 5)()
-    L.check(lib.rad_profile_read(profs, 5), "rad_profile_read")
+    profs = (L.RadKernelProfile * NK)()
+    L.check(lib.rad_profile_read(profs, NK), "rad_profile_read")
     lib.rad_profile_enable(0)
     ms_step = total_ms / args.steps
     chk_h = chk.cpu().numpy()
@@ -193,9 +248,11 @@ def main() -> int:
     pk = profs[L.PROFILE_KINDS.index(dom)]
     achieved = pk.flops / pk.launches / (pk.total_ms / pk.launches * 1e-3) / 1e12
     peak = PEAK_TFLOPS["fp64" if dom == "gemm_f64" else "fp32"]
-    roofline = {"bound": "mfma", "kernel": f"gemm_mfma<{'double' if dom == 'gemm_f64' else 'float'}>",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
+    kname = f"gemm_lds<{'double' if dom == 'gemm_f64' else 'float'}, false>"
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(kname, prec),
+                "algorithmic_bytes_per_launch": pk.bytes / pk.launches,
+                "flops_per_launch": pk.flops / pk.launches, "avg_launch_us": 1000.0 * pk.total_ms / pk.launches}
     sw = profs[L.PROFILE_KINDS.index("enforce_sweep")]
     if sw.launches:
         kern["enforce_sweep"]["hbm_frac"] = (sw.bytes / (sw.total_ms * 1e-3) / 1e9) / PEAK_HBM_GBS
@@ -205,7 +262,7 @@ def main() -> int:
         import threadpoolctl
         threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
         f_in = inst.f_noisy
-        k_iter = 2
+        k_iter = 1
         t = time.perf_counter()
         oracle.enforce_vf(f_in, inst.area, inst.n_rays, "fracvar", tol=0.0, max_iter=k_iter)
         t_enf_iter = (time.perf_counter() - t) / k_iter
@@ -240,7 +297,7 @@ def main() -> int:
         "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "open_box_n8192 (1x1x0.25 m, 1/64 m cells, 1e4 rays/face) full pipeline",
-                   "n": n, "precision": prec, "kappa": "fracvar", "enforce_tol": ENF_TOL,
+                   "n": n, "precision": prec, "ir_steps_max": ir_max, "kappa": "fracvar", "enforce_tol": ENF_TOL,
                    "enforce_iters": est["iters"], "aggregation": f"{n}->{n1}->{n2}",
                    "parallelism": "single GPU"},
         "roofline": roofline,

@@ -261,7 +261,8 @@ void rad_batch_plan_destroy(rad_batch_plan* plan);
  * thread bracket every launch of the kernels below with two events on the
  * launch's stream; rad_profile_read waits for the recorded events, writes
  * per-kind totals into out[0..count) and resets them.  flops / bytes are the
- * algorithmic work of the launches (2 M N K for a GEMM; one read and one write
+ * algorithmic work of the launches (2 M N K flops and one pass over A, B and C
+ * for a GEMM, C read too when accumulated; one read and one write
  * of the n x (n+1) matrix for an enforcement sweep; one read of it for an
  * aggregation).  Profiling adds two event records per launch.
  */
@@ -270,7 +271,9 @@ void rad_batch_plan_destroy(rad_batch_plan* plan);
 #define RAD_PROF_ENFORCE_SWEEP 2 /* enforcement sweep                                */
 #define RAD_PROF_DIAG_INVERSE 3  /* Gauss-Jordan inverse of a diagonal block         */
 #define RAD_PROF_AGGREGATE 4     /* aggregation reduction                            */
-#define RAD_PROF_KINDS 5
+#define RAD_PROF_GEMM_F64_T 5    /* FP64 MFMA GEMM with transposed A (adjoint)       */
+#define RAD_PROF_GEMM_F32_T 6    /* FP32 MFMA GEMM with transposed A (adjoint)       */
+#define RAD_PROF_KINDS 7
 
 typedef struct rad_kernel_profile {
   int64_t launches;

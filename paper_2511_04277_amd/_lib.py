@@ -69,7 +69,8 @@ class RadInstance(ctypes.Structure):
     ]
 
 
-PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate"]
+PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate", "gemm_f64_t",
+                 "gemm_f32_t"]
 
 
 class RadError(RuntimeError):

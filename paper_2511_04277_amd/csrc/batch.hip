@@ -37,7 +37,7 @@ struct rad_batch_plan {
   std::vector<ProbOff> po;
   size_t tables_off = 0;
   // launch schedule (table offsets relative to the tables block)
-  struct Launch { int kind; int trans; unsigned grid; size_t off, off2; int count; double flops; };
+  struct Launch { int kind; int trans; unsigned grid; size_t off, off2; int count; double flops, bytes; };
   std::vector<Launch> factor, back, fwd, resid;
   size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
   double sweep_bytes = 0.0;  // algorithmic bytes of one sweep over every instance
@@ -245,10 +245,11 @@ struct Sched {
   void emit_gemm(std::vector<rad_batch_plan::Launch>& out, std::vector<GemmArgs<T>>& a, bool trans) {
     if (a.empty()) return;
     std::vector<int> ts(a.size() + 1, 0);
-    double flops = 0.0;
+    double flops = 0.0, bytes = 0.0;
     for (size_t k = 0; k < a.size(); ++k) {
       ts[k + 1] = ts[k] + gemm_tiles<T>(a[k]);
-      for (int q = 0; q < a[k].nseg; ++q) flops += 2.0 * a[k].M * a[k].N[q] * a[k].K;
+      flops += gemm_flops(a[k]);
+      bytes += gemm_bytes(a[k]);
     }
     if (ts.back() == 0) {
       a.clear();
@@ -256,6 +257,7 @@ struct Sched {
     }
     rad_batch_plan::Launch L{};
     L.flops = flops;
+    L.bytes = bytes;
     L.kind = L_GEMM;
     L.trans = trans ? 1 : 0;
     L.count = static_cast<int>(a.size());
@@ -430,13 +432,15 @@ struct Sched {
       g.push_back(a);
     }
     std::vector<int> ts(g.size() + 1, 0);
-    double flops = 0.0;
+    double flops = 0.0, bytes = 0.0;
     for (size_t k = 0; k < g.size(); ++k) {
       ts[k + 1] = ts[k] + gemm_tiles<double>(g[k]);
-      flops += 2.0 * g[k].M * g[k].N[0] * g[k].K;
+      flops += gemm_flops(g[k]);
+      bytes += gemm_bytes(g[k]);
     }
     rad_batch_plan::Launch L{};
     L.flops = flops;
+    L.bytes = bytes;
     L.kind = L_GEMM;
     L.count = static_cast<int>(g.size());
     L.off = tb->add(g.data(), g.size());
@@ -594,7 +598,7 @@ hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const cha
       hipLaunchKernelGGL(gj_batched<T>, dim3(L.grid), dim3(GJ_THREADS), 0, s,
                          reinterpret_cast<const GjJob<T>*>(tables + L.off));
     } else {
-      ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32, L.flops, 0.0);
+      ProfScope prof(s, gemm_prof_kind<T>(L.trans != 0), L.flops, L.bytes);
       const GemmArgs<T>* a = reinterpret_cast<const GemmArgs<T>*>(tables + L.off);
       const int* ts = reinterpret_cast<const int*>(tables + L.off2);
       if (L.trans)

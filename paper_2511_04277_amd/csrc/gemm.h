@@ -247,6 +247,27 @@ inline int gemm_tiles(GemmArgs<T>& a) {
   return total * ((a.M + GEMM_TILE - 1) / GEMM_TILE);
 }
 
+// Profiling kind and algorithmic work of one product (A read once, B read
+// once, C written once and also read when beta != 0).
+template <class T>
+inline int gemm_prof_kind(bool trans_a) {
+  if (sizeof(T) == 8) return trans_a ? RAD_PROF_GEMM_F64_T : RAD_PROF_GEMM_F64;
+  return trans_a ? RAD_PROF_GEMM_F32_T : RAD_PROF_GEMM_F32;
+}
+template <class T>
+inline double gemm_flops(const GemmArgs<T>& a) {
+  double ncols = 0.0;
+  for (int q = 0; q < a.nseg; ++q) ncols += a.N[q];
+  return 2.0 * a.M * ncols * a.K;
+}
+template <class T>
+inline double gemm_bytes(const GemmArgs<T>& a) {
+  double ncols = 0.0;
+  for (int q = 0; q < a.nseg; ++q) ncols += a.N[q];
+  const double c = (a.beta != T(0) ? 2.0 : 1.0) * a.M * ncols;
+  return sizeof(T) * (static_cast<double>(a.M) * a.K + static_cast<double>(a.K) * ncols + c);
+}
+
 // Host-side launcher: one or two column segments.
 template <class T>
 inline hipError_t launch_gemm(const GemmArgs<T>& a0, bool trans_a, hipStream_t s) {
@@ -259,10 +280,7 @@ inline hipError_t launch_gemm(const GemmArgs<T>& a0, bool trans_a, hipStream_t s
   }
   if (total == 0) return hipSuccess;
   dim3 grid(static_cast<unsigned>(total), static_cast<unsigned>((a.M + GEMM_TILE - 1) / GEMM_TILE));
-  double ncols = 0.0;
-  for (int q = 0; q < a.nseg; ++q) ncols += a.N[q];
-  ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32,
-                 2.0 * a.M * ncols * a.K, 0.0);
+  ProfScope prof(s, gemm_prof_kind<T>(trans_a), gemm_flops(a), gemm_bytes(a));
   if (trans_a)
     hipLaunchKernelGGL((gemm_lds<T, true>), grid, dim3(256), 0, s, a);
   else
