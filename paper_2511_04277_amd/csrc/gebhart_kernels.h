@@ -141,17 +141,20 @@ __global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) 
     p[q] = T(0);
 }
 
-// Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting.  Thread t
-// keeps column j = t % NB of the 16 contiguous rows g*16 .. g*16+15
-// (g = t / NB) in registers.  Step p is one uniform update
-//   m_ij <- m_ij - c_i r_j,   r_j = m_pj d (j != p), r_p = d = 1 / m_pp,
-//                             c_i = m_ip (i != p),   c_p = -1,
-// after row p and column p have been published through LDS and zeroed in
-// registers: that yields the new row p (r), column p (-c d) and pivot (d) of
-// the in-place inverse with one FMA per element.  Pivots are taken in the
-// order p = g*16 + q (q outer), which keeps register indices static; any
-// order of diagonal pivots gives the same inverse and diagonal dominance
-// makes every order stable.  LDS is double-buffered, one barrier per step.
+// Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting, blocked by
+// 16.  The block is held as 8 x 8 tiles of 16 x 16 in MFMA accumulator layout:
+// wave w (of 16) owns tile row w/2, tile columns (w%2)*4 .. +3.  Step s takes
+// the 16 x 16 pivot tile P = M(s,s) and applies
+//   M(s,s) <- P^-1,   M(s,j) <- P^-1 M(s,j),   M(i,s) <- -M(i,s) P^-1,
+//   M(i,j) <- M(i,j) - M(i,s) P^-1 M(s,j)                 (i, j != s),
+// i.e. the scalar in-place Gauss-Jordan update with a 16 x 16 pivot; after
+// the 8 steps M = A^-1.  P is inverted inside one wave by 16 scalar
+// Gauss-Jordan steps with lane j holding column j (pivot row and column are
+// broadcast with lane reads, no barriers); the row products and the rank-16
+// updates run on the matrix cores.  Two workgroup barriers per step.
+// Diagonal dominance of K makes every pivot order stable, so no pivoting is
+// needed; the scalar pivots are the same Schur-complement diagonals as in
+// unblocked elimination and are checked against the singularity threshold.
 constexpr int GJ_THREADS = 1024;
 
 // 1/x: hardware reciprocal refined by Newton steps to full precision
@@ -166,55 +169,137 @@ __device__ __forceinline__ float recip_nr(float x) {
   return r * (2.0f - x * r);
 }
 
+// value of x in lane `lane` (uniform), broadcast to the wave
+__device__ __forceinline__ double lane_read(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(v), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(v >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ float lane_read(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// orders this wave's LDS writes before its later LDS reads
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <class T>
 __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
-  constexpr int G = GJ_THREADS / NB;  // 8 row groups
-  constexpr int R = NB / G;           // 16 rows per thread
-  __shared__ T sRow[2][NB];
-  __shared__ __attribute__((aligned(16))) T sCol[2][NB];
-  const int tid = threadIdx.x;
-  const int j = tid & (NB - 1);
-  const int g = tid / NB;
-  T m[R];
+  typedef typename Mfma<T>::v4 v4;
+  constexpr int BT = 16;              // pivot tile
+  constexpr int NT = NB / BT;         // 8 tiles per side
+  constexpr int LC = BT + 2;          // padded row of the column panel
+  constexpr int LR = NB + 2;          // padded row of the row panels
+  __shared__ T sC[2][NB][LC];         // old tile column s (double-buffered)
+  __shared__ T sRo[BT][LR];           // old tile row s
+  __shared__ T sR[BT][LR];            // new tile row s (R(s) = P^-1)
+  __shared__ T sP[BT][BT + 1];        // P^-1, row-major
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int li = l & 15, lg = l >> 4;
+  const int bi = w >> 1, bj0 = (w & 1) * 4;
+  v4 m[4];
 #pragma unroll
-  for (int q = 0; q < R; ++q) m[q] = A[static_cast<long>(g * R + q) * lda + j];
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      m[b][r] = A[static_cast<long>(bi * BT + Mfma<T>::orow(l, r)) * lda + (bj0 + b) * BT + li];
   const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
   int singular = 0;
-#pragma unroll
-  for (int q0 = 0; q0 < R; ++q0) {
 #pragma unroll 1
-    for (int gg = 0; gg < G; ++gg) {
-      const int p = gg * R + q0;
-      const int buf = gg & 1;  // alternates every step (G is even)
-      if (g == gg) {  // owner of row p publishes it and clears it
-        sRow[buf][j] = m[q0];
-        m[q0] = T(0);
-      }
-      if (j == p) {   // owner of column p publishes it (c_p = -1) and clears it
+  for (int s = 0; s < NT; ++s) {
+    const int cb = s & 1;
+    const bool has_col = (s >= bj0) && (s < bj0 + 4);
+    // publish the old tile column s and tile row s
+    if (has_col) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          sCol[buf][g * R + q] = (g == gg && q == q0) ? T(-1) : m[q];
-          m[q] = T(0);
+      for (int b = 0; b < 4; ++b)
+        if (bj0 + b == s)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sC[cb][bi * BT + Mfma<T>::orow(l, r)][li] = m[b][r];
+    }
+    if (bi == s) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sRo[Mfma<T>::orow(l, r)][(bj0 + b) * BT + li] = m[b][r];
+    }
+    // the owner of the pivot tile inverts it (lane j keeps column j)
+    if (bi == s && has_col) {
+      wave_lds_sync();
+      const int j = li;
+      T c[BT];
+#pragma unroll
+      for (int i = 0; i < BT; ++i) c[i] = sRo[i][s * BT + j];
+#pragma unroll
+      for (int q = 0; q < BT; ++q) {
+        const T piv = lane_read(c[q], q);
+        T d = recip_nr(piv);
+        if (!(fabs(static_cast<double>(piv)) > tiny) || !(fabs(static_cast<double>(d)) < 1e300)) {
+          singular = 1;
+          d = T(0);
         }
-      }
-      __syncthreads();
-      const T piv = sRow[buf][p];
-      T d = recip_nr(piv);
-      // K has unit diagonal scale and its pivots stay >= 1 - max rho for
-      // valid input; a pivot below this threshold means a singular K.
-      if (!(fabs(static_cast<double>(piv)) > tiny) || !(fabs(static_cast<double>(d)) < 1e300)) {
-        singular = 1;
-        d = T(0);
-      }
-      const T rj = (j == p) ? d : sRow[buf][j] * d;
-      const T* col = &sCol[buf][g * R];
+        T colq[BT];
 #pragma unroll
-      for (int q = 0; q < R; ++q) m[q] = m[q] - col[q] * rj;
+        for (int i = 0; i < BT; ++i) colq[i] = (i == q) ? T(-1) : lane_read(c[i], q);
+        const T rj = (j == q) ? d : c[q] * d;
+        if (j == q) {
+#pragma unroll
+          for (int i = 0; i < BT; ++i) c[i] = T(0);
+        }
+        c[q] = T(0);
+#pragma unroll
+        for (int i = 0; i < BT; ++i) c[i] = c[i] - colq[i] * rj;
+      }
+      if (l < BT) {
+#pragma unroll
+        for (int i = 0; i < BT; ++i) sP[i][j] = c[i];
+      }
+    }
+    __syncthreads();
+    // new tile row s: R(s, j) = P^-1 Ro(s, j), R(s, s) = P^-1
+    if (bi == s) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int jt = bj0 + b;
+        if (jt == s) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m[b][r] = sP[Mfma<T>::orow(l, r)][li];
+        } else {
+          v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            acc = Mfma<T>::mma(sP[li][4 * kk + lg], sRo[4 * kk + lg][jt * BT + li], acc);
+          m[b] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][jt * BT + li] = m[b][r];
+      }
+    }
+    __syncthreads();
+    // rank-16 update of the other tile rows; tile column s becomes -M(i,s) P^-1
+    if (bi != s) {
+      T a[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a[kk] = -sC[cb][bi * BT + li][4 * kk + lg];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int jt = bj0 + b;
+        if (jt == s) m[b] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) m[b] = Mfma<T>::mma(a[kk], sR[4 * kk + lg][jt * BT + li], m[b]);
+      }
     }
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q) out[(g * R + q) * NB + j] = m[q];
-  if (singular && tid == 0) raise_status(&sc->status, RAD_ESINGULAR);
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      out[(bi * BT + Mfma<T>::orow(l, r)) * NB + (bj0 + b) * BT + li] = m[b][r];
+  if (singular) raise_status(&sc->status, RAD_ESINGULAR);
 }
 
 template <class T>
