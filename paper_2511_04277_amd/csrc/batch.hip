@@ -204,21 +204,25 @@ b_apply_correction(const ProbDesc* __restrict__ pd, const long* __restrict__ sta
 template <class T, bool TRANS_A>
 __global__ void __launch_bounds__(256, 2)
 gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
+  // the grid is the tile count or a multiple of 8, so every tile b this
+  // workgroup takes runs on XCD b % 8, as xcd_contiguous assumes
   const int total = tile_start[nprob];
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const int t = xcd_contiguous(b, total);
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+      if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
     }
     const GemmArgs<T>& g = probs[lo];
-    const int local = b - tile_start[lo];
     const int ntx = g.ntile[0] + g.ntile[1];
-    gemm_tile<T, TRANS_A>(g, local % ntx, local / ntx);
+    int bx, by;
+    grouped_tile(t - tile_start[lo], ntx, (g.M + GEMM_TILE - 1) / GEMM_TILE, bx, by);
+    gemm_tile<T, TRANS_A>(g, bx, by);
   }
 }
 
-constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU
+constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU (a multiple of 8)
 
 // ------------------------------------------------------------- host side ---
 struct TableBuilder {

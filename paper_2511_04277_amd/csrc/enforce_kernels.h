@@ -22,17 +22,6 @@ struct EnfCtrl {
   double last_defect, last_recip;
 };
 
-__device__ inline double kappa_of(double fij, double fji, double ai, double aj,
-                                  double ni, double nj, int mode) {
-  if (mode == RAD_KAPPA_HALF) return 0.5;
-  // eq. 3.25 with s2_ij = A_i^2 (1-F_ij)/(N_i F_ij); numerator and
-  // denominator multiplied by F_ij F_ji so that zeros need no infinities.
-  double a = ai * ai * (1.0 - fij) * fji / ni;
-  double b = aj * aj * (1.0 - fji) * fij / nj;
-  double s = a + b;
-  return s > 0.0 ? b / s : 0.5;
-}
-
 __device__ inline void pair_from_index(long p, int t, int& I, int& J) {
   // row-wise enumeration of the upper triangle (I <= J) of a t x t tile grid
   double tt = 2.0 * t + 1.0;
@@ -46,9 +35,6 @@ __device__ inline void pair_from_index(long p, int t, int& I, int& J) {
   J = static_cast<int>(i + (p - start(i)));
 }
 
-// Thread t owns row r = t / 4 of the 64 x 64 tile (I, J) and its 16
-// consecutive columns cq*16 .. cq*16+15 (cq = t % 4) in registers; the partner
-// tile (J, I) sits in LDS.  Both tiles are read and written as 128-byte runs.
 // One enforcement problem as the kernels see it.
 struct EnfInst {
   double* F;
@@ -65,188 +51,233 @@ struct EnfInst {
   EnfCtrl* ctrl;
 };
 
-__device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int first) {
+constexpr int ERW = ET / (ENF_THREADS / 64);  // 16 tile rows per wave
+
+// Element col of a row whose base pointer is wave-uniform: the byte offset
+// is a 32-bit lane value, so loads and stores take the scalar-base form and
+// one offset register serves every row.
+// (readfirstlane pins the row pointer to scalar registers, so the compiler
+// cannot fold the lane offset into a per-row vector address).
+__device__ __forceinline__ char* uniform_ptr(const double* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+  return reinterpret_cast<char*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double row_ld(const double* row, unsigned col) {
+  return *reinterpret_cast<const double*>(uniform_ptr(row) + col * 8u);
+}
+__device__ __forceinline__ void row_st(double* row, unsigned col, double v) {
+  *reinterpret_cast<double*>(uniform_ptr(row) + col * 8u) = v;
+}
+
+// kappa of eq. 3.25 from the pair (f_ij, f_ji) and c = A^2 / N of both faces:
+// kappa = b / (a + b), a = c_i (1 - f_ij) f_ji, b = c_j (1 - f_ji) f_ij (the
+// variances of eq. 3.23 multiplied by F_ij F_ji); 1/2 when both vanish.
+// The quotient uses the hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double kappa_c(double fij, double fji, double ci, double cj) {
+  const double a = ci * (1.0 - fij) * fji;
+  const double b = cj * (1.0 - fji) * fij;
+  const double s = a + b;
+  double r = __builtin_amdgcn_rcp(s);
+  r = r * (2.0 - s * r);
+  r = r * (2.0 - s * r);
+  return s > 0.0 ? b * r : 0.5;
+}
+
+// One workgroup per tile pair (I, J), I <= J, of 64 x 64 tiles.  Lane l of
+// wave w holds column l of tile rows w, w + 4, ..., w + 60, so every load and
+// store instruction of a wave moves one contiguous 512-byte tile row.  The
+// partner tile (J, I) is staged through LDS (65-double rows), where each
+// unordered pair {i, j} meets its mirror; the previous iteration's closure
+// scale 1 / s_i is applied on load.  The thread that updates pair (i, j)
+// also produces the partner's entry (j, i), and its 16 pairs all lie in one
+// partner row, so the partner's row sums are formed in registers; the own
+// tile's rows are summed after a transpose through the same LDS buffer.
+// All sums run in a fixed order (bitwise reproducible).  DIAG: I == J (each
+// unordered pair once, the diagonal kept, the space column carried along);
+// EDGE: the tile pair crosses n (clamped loads, masked stores).
+template <bool DIAG, bool EDGE>
+__device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int I, int J, int first,
+                                               double (*sB)[ETP], double (*red)[ET], double (*rowc)[ET]) {
   double* __restrict__ F = in.F;
   const long ldf = in.ldf;
-  const int n = in.n, t = in.t;
+  const int n = in.n;
   const double* __restrict__ area = in.area;
   const double* __restrict__ inv_area = in.inv_area;
   const double* __restrict__ nrays = in.nrays;
-  const int mode = in.mode;
+  const bool half = in.mode == RAD_KAPPA_HALF;
   const double* __restrict__ inv_scale = in.scale;
-  double* __restrict__ partial = in.partial;
-  double* __restrict__ blkmax = in.blkmax;
-  EnfCtrl* ctrl = in.ctrl;
-  if (ctrl->converged || ctrl->status < 0) return;
-  __shared__ double sB[ET][ETP];
-  __shared__ double red[2][ENF_THREADS / 64];
-  int I, J;
-  pair_from_index(pair, t, I, J);
   const int r0 = I * ET, c0 = J * ET;
   const int tid = threadIdx.x;
-  const int r = tid >> 2, cq = tid & 3, cb = cq * 16;
-  const bool diag = (I == J);
-  const int i = r0 + r;          // this thread's row of tile (I, J)
-  const int ip = c0 + r;         // this thread's row of the partner tile (J, I)
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   int bad = 0;
 
-  // Interior tiles (the vast majority) load and store unconditionally; edge
-  // tiles clamp their addresses and zero the entries beyond n, which the pair
-  // arithmetic below leaves at zero.
-  const bool interior = (r0 + ET <= n) && (c0 + ET <= n);
-  double a[16];
-  {
-    const int ic = i < n ? i : n - 1;
-    const double si = first ? 1.0 : inv_scale[ic];
-    const double* src = F + static_cast<long>(ic) * ldf;
-    if (interior) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) a[e] = src[c0 + cb + e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = c0 + cb + e;
-        const double v = src[j < n ? j : n - 1];
-        a[e] = (i < n && j < n) ? v : 0.0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      bad |= !(a[e] >= 0.0) || !(a[e] <= 1.0e300);
-      a[e] *= si;
-    }
+  // per-row constants of tile row block I: area, 1 / area, A^2 / N, 1 / s
+  if (tid < ET) {
+    const int i = (EDGE && r0 + tid >= n) ? n - 1 : r0 + tid;
+    const double ai = area[i];
+    rowc[0][tid] = ai;
+    rowc[1][tid] = inv_area[i];
+    rowc[2][tid] = half ? 0.0 : ai * ai / nrays[i];
+    rowc[3][tid] = first ? 1.0 : inv_scale[i];
+  } else if (!DIAG && tid < 2 * ET) {  // 1 / s of the partner tile's rows
+    const int jr = (EDGE && c0 + tid - ET >= n) ? n - 1 : c0 + tid - ET;
+    rowc[4][tid - ET] = first ? 1.0 : inv_scale[jr];
   }
-  if (!diag) {
-    const int ipc = ip < n ? ip : n - 1;
-    const double sj = first ? 1.0 : inv_scale[ipc];
-    const double* src = F + static_cast<long>(ipc) * ldf;
-    double v[16];
-    if (interior) {
+  __syncthreads();
+  // own tile (I, J): a[k] = F(r0 + w + 4k, c0 + l).  Row pointers are
+  // wave-uniform and the lane adds its column, so loads use a scalar base.
+  const int jg = c0 + l;
+  const int jgc = (EDGE && jg >= n) ? n - 1 : jg;
+  double a[ERW];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) v[e] = src[r0 + cb + e];
-    } else {
+  for (int k = 0; k < ERW; ++k) {
+    const int i = r0 + w + 4 * k;
+    const int ic = (EDGE && i >= n) ? n - 1 : i;
+    double v = row_ld(F + static_cast<long>(ic) * ldf, jgc);
+    if (EDGE && !(i < n && jg < n)) v = 0.0;
+    bad |= !(v >= 0.0) || !(v <= 1.0e300);
+    a[k] = v * rowc[3][w + 4 * k];
+  }
+  // partner tile (J, I) into LDS: sB[jl][il] = F(c0 + jl, r0 + il)
+  if (!DIAG) {
+    const int ig = r0 + l;
+    const int igc = (EDGE && ig >= n) ? n - 1 : ig;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = r0 + cb + e;
-        const double x = src[j < n ? j : n - 1];
-        v[e] = (ip < n && j < n) ? x : 0.0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      bad |= !(v[e] >= 0.0) || !(v[e] <= 1.0e300);
-      sB[r][cb + e] = v[e] * sj;
+    for (int k = 0; k < ERW; ++k) {
+      const int jr = c0 + w + 4 * k;
+      const int jrc = (EDGE && jr >= n) ? n - 1 : jr;
+      double v = row_ld(F + static_cast<long>(jrc) * ldf, igc);
+      if (EDGE && !(jr < n && ig < n)) v = 0.0;
+      bad |= !(v >= 0.0) || !(v <= 1.0e300);
+      sB[w + 4 * k][l] = v * rowc[4][w + 4 * k];
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sB[r][cb + e] = a[e];
+    for (int k = 0; k < ERW; ++k) sB[w + 4 * k][l] = a[k];
   }
   __syncthreads();
 
   // reciprocity on each unordered pair {i, j}, i != j, exactly once
-  double rmax = 0.0, emax = 0.0;
-  const int ic = i < n ? i : n - 1;
-  const double ai = area[ic];
-  const double iai = inv_area[ic];
-  const double ni = nrays ? nrays[ic] : 1.0;
+  double rmax = 0.0, emax = 0.0, sb = 0.0;
+  const double aj = area[jgc], iaj = inv_area[jgc];
+  const double cj = half ? 0.0 : aj * aj / nrays[jgc];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int c = cb + e;
-    const int j = c0 + c;
-    const int jc = j < n ? j : n - 1;
-    if (diag) {
-      if (c == r) emax = fmax(emax, ai * a[e]);  // diagonal keeps its value
-      if (c <= r) continue;                       // handled by the owner of (c, r)
+  for (int k = 0; k < ERW; ++k) {
+    const int il = w + 4 * k;
+    const double ai = rowc[0][il];
+    if (DIAG) {
+      if (l == il) emax = fmax(emax, ai * a[k]);  // the diagonal keeps its value
+      if (l <= il) continue;                       // handled by the owner of (l, il)
     }
-    const double fij = a[e], fji = sB[c][r];
-    const double aj = area[jc];
+    const double iai = rowc[1][il];
+    const double fij = a[k], fji = sB[l][il];
     const double eij = ai * fij, eji = aj * fji;
     rmax = fmax(rmax, fabs(eij - eji));
     emax = fmax(emax, fmax(eij, eji));
-    const double nj = nrays ? nrays[jc] : 1.0;
-    const double k = kappa_of(fij, fji, ai, aj, ni, nj, mode);
-    const double eh = k * eij + (1.0 - k) * eji;
-    a[e] = eh * iai;
-    sB[c][r] = eh * inv_area[jc];
+    const double kp = half ? 0.5 : kappa_c(fij, fji, rowc[2][il], cj);
+    const double eh = kp * eij + (1.0 - kp) * eji;
+    const double bji = eh * iaj;
+    a[k] = eh * iai;
+    sB[l][il] = bji;
+    sb += bji;
+    // keep the 16 pair updates from being interleaved (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
-  if (diag) {
+  if (DIAG) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
-      if (cb + e < r) a[e] = sB[r][cb + e];  // lower-triangle values written by their pair owner
+    for (int k = 0; k < ERW; ++k)
+      if (l < w + 4 * k) a[k] = sB[w + 4 * k][l];  // written by the owner of the mirror
   }
 
-  // write back and form the partial row sums (4-lane reductions, fixed order)
-  double sa = 0.0, sb = 0.0;
+  // own tile back to F
 #pragma unroll
-  for (int e = 0; e < 16; ++e) sa += a[e];
-  if (interior) {
-    double* dst = F + static_cast<long>(i) * ldf + c0 + cb;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) dst[e] = a[e];
-  } else if (i < n) {
-    double* dst = F + static_cast<long>(i) * ldf + c0 + cb;
-#pragma unroll
-    for (int e = 0; e < 16; ++e)
-      if (c0 + cb + e < n) dst[e] = a[e];
+  for (int k = 0; k < ERW; ++k) {
+    const int i = r0 + w + 4 * k;
+    if (!EDGE || (i < n && jg < n)) row_st(F + static_cast<long>(i) * ldf, jg, a[k]);
   }
-  if (!diag) {
-    double v[16];
+  if (!DIAG) {  // partner tile back to F
+    const int ig = r0 + l;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      v[e] = sB[r][cb + e];
-      sb += v[e];
-    }
-    double* dst = F + static_cast<long>(ip) * ldf + r0 + cb;
-    if (interior) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) dst[e] = v[e];
-    } else if (ip < n) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        if (r0 + cb + e < n) dst[e] = v[e];
+    for (int k = 0; k < ERW; ++k) {
+      const int jr = c0 + w + 4 * k;
+      if (!EDGE || (jr < n && ig < n)) row_st(F + static_cast<long>(jr) * ldf, ig, sB[w + 4 * k][l]);
     }
   }
-  sa += __shfl_xor(sa, 1);
-  sa += __shfl_xor(sa, 2);
-  sb += __shfl_xor(sb, 1);
-  sb += __shfl_xor(sb, 2);
-  if (cq == 0) {
-    if (i < n) {
-      partial[static_cast<long>(J) * n + i] = sa;
-      if (diag) {  // the space column of row i rides with the diagonal tile
-        double* sp = F + static_cast<long>(i) * ldf + n;
-        double v = *sp;
-        bad |= !(v >= 0.0) || !(v <= 1.0e300);
-        if (!first) v *= inv_scale[i];
-        *sp = v;
-        partial[static_cast<long>(t) * n + i] = v;
-      }
-    }
-    if (!diag && ip < n) partial[static_cast<long>(I) * n + ip] = sb;
-  }
-  if (bad) raise_status(&ctrl->status, RAD_ENONFINITE);
+  __syncthreads();
+  // own tile transposed into LDS, then each thread sums 16 entries of row l
+#pragma unroll
+  for (int k = 0; k < ERW; ++k) sB[l][w + 4 * k] = a[k];
+  red[w][l] = sb;  // partner row l: this wave's 16 entries
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_xor(rmax, off));
     emax = fmax(emax, __shfl_xor(emax, off));
   }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = rmax;
-    red[1][tid >> 6] = emax;
+  __syncthreads();
+  double sa = 0.0;
+#pragma unroll
+  for (int k = 0; k < ERW; ++k) sa += sB[w + 4 * k][l];
+  __syncthreads();
+  red[ENF_THREADS / 64 + w][l] = sa;  // own row l: this wave's 16 entries
+  if (l == 0) {
+    sB[0][w] = rmax;
+    sB[1][w] = emax;
   }
   __syncthreads();
-  if (tid == 0) {
-    double x = red[0][0], y = red[1][0];
-    for (int w = 1; w < ENF_THREADS / 64; ++w) {
-      x = fmax(x, red[0][w]);
-      y = fmax(y, red[1][w]);
+  if (w == 0) {
+    double s_own = 0.0, s_par = 0.0;
+#pragma unroll
+    for (int q = 0; q < ENF_THREADS / 64; ++q) {
+      s_own += red[ENF_THREADS / 64 + q][l];
+      s_par += red[q][l];
     }
-    blkmax[2 * pair] = x;
-    blkmax[2 * pair + 1] = y;
+    const int t = in.t;
+    double* __restrict__ partial = in.partial;
+    if (!EDGE || r0 + l < n) partial[static_cast<long>(J) * n + r0 + l] = s_own;
+    if (!DIAG && (!EDGE || c0 + l < n)) partial[static_cast<long>(I) * n + c0 + l] = s_par;
+    if (DIAG && (!EDGE || r0 + l < n)) {  // the space column of the tile's rows rides with the diagonal tile
+      double* sp = F + static_cast<long>(r0 + l) * ldf + n;
+      double v = *sp;
+      bad |= !(v >= 0.0) || !(v <= 1.0e300);
+      v *= rowc[3][l];
+      *sp = v;
+      partial[static_cast<long>(t) * n + r0 + l] = v;
+    }
+    if (l == 0) {
+      double x = sB[0][0], y = sB[1][0];
+      for (int q = 1; q < ENF_THREADS / 64; ++q) {
+        x = fmax(x, sB[0][q]);
+        y = fmax(y, sB[1][q]);
+      }
+      in.blkmax[2 * pair] = x;
+      in.blkmax[2 * pair + 1] = y;
+    }
+  }
+  if (bad) raise_status(&in.ctrl->status, RAD_ENONFINITE);
+}
+
+__device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int first) {
+  if (in.ctrl->converged || in.ctrl->status < 0) return;
+  __shared__ double sB[ET][ETP];
+  __shared__ double red[2 * (ENF_THREADS / 64)][ET];  // per-wave row partials: partner, own
+  __shared__ double rowc[5][ET];                       // per-row constants
+  int I, J;
+  pair_from_index(pair, in.t, I, J);
+  I = __builtin_amdgcn_readfirstlane(I);  // workgroup-uniform: keeps tile addressing scalar
+  J = __builtin_amdgcn_readfirstlane(J);
+  const bool edge = (I + 1) * ET > in.n || (J + 1) * ET > in.n;
+  if (I == J) {
+    if (edge) enf_sweep_tile<true, true>(in, pair, I, J, first, sB, red, rowc);
+    else enf_sweep_tile<true, false>(in, pair, I, J, first, sB, red, rowc);
+  } else {
+    if (edge) enf_sweep_tile<false, true>(in, pair, I, J, first, sB, red, rowc);
+    else enf_sweep_tile<false, false>(in, pair, I, J, first, sB, red, rowc);
   }
 }
 
-__global__ void __launch_bounds__(ENF_THREADS) enf_sweep(EnfInst in, int first) {
+__global__ void __launch_bounds__(ENF_THREADS, 2) enf_sweep(EnfInst in, int first) {
   enf_sweep_body(in, blockIdx.x, first);
 }
 
@@ -261,7 +292,7 @@ __device__ __forceinline__ int find_segment(const long* __restrict__ start, int 
 }
 
 // all instances of a batch in one grid: blocks [pair_start[k], pair_start[k+1]) are instance k
-__global__ void __launch_bounds__(ENF_THREADS)
+__global__ void __launch_bounds__(ENF_THREADS, 2)
 enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair_start, int count, int first) {
   const int k = find_segment(pair_start, count, blockIdx.x);
   enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);

@@ -101,6 +101,18 @@ struct GemmCfg {
   static constexpr int EPT = KC / 2;  // slab elements per thread per operand
 };
 
+// LDS slab of op(A) for one K chunk: row-major [128][KC] when A is read by
+// rows; K-major [KC][128] when op(A) is a transpose (its global rows are k),
+// so both cases store 16-byte runs without bank conflicts.
+template <class T, bool TRANS_A>
+struct ASlab {
+  static constexpr int R = GEMM_TILE, C = GemmCfg<T>::KC + GemmCfg<T>::PA;
+};
+template <class T>
+struct ASlab<T, true> {
+  static constexpr int R = GemmCfg<T>::KC, C = GEMM_TILE + GemmCfg<T>::PB;
+};
+
 template <class T, int NE>
 __device__ __forceinline__ void loadv(const T* __restrict__ src, T (&r)[NE]) {
   typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
@@ -130,7 +142,7 @@ __device__ __forceinline__ void lds_stage_load(const T* __restrict__ A, long lda
 }
 
 template <class T, bool TRANS_A>
-__device__ __forceinline__ void lds_stage_store(T (*sA)[GemmCfg<T>::KC + GemmCfg<T>::PA],
+__device__ __forceinline__ void lds_stage_store(T (*sA)[(ASlab<T, TRANS_A>::C)],
                                                 T (*sB)[GEMM_TILE + GemmCfg<T>::PB],
                                                 const T (&ra)[GemmCfg<T>::EPT], const T (&rb)[GemmCfg<T>::EPT]) {
   constexpr int E = GemmCfg<T>::EPT;
@@ -143,7 +155,7 @@ __device__ __forceinline__ void lds_stage_store(T (*sA)[GemmCfg<T>::KC + GemmCfg
   } else {
     const int k = t / TPR, mb = (t % TPR) * E;
 #pragma unroll
-    for (int q = 0; q < E; ++q) sA[mb + q][k] = ra[q];
+    for (int q = 0; q < E; ++q) sA[k][mb + q] = ra[q];
   }
   const int k = t / TPR, nb = (t % TPR) * E;
 #pragma unroll
@@ -156,7 +168,7 @@ template <class T, bool TRANS_A>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
-  __shared__ T sA[2][GEMM_TILE][KC + GemmCfg<T>::PA];
+  __shared__ T sA[2][ASlab<T, TRANS_A>::R][ASlab<T, TRANS_A>::C];
   __shared__ T sB[2][KC][GEMM_TILE + GemmCfg<T>::PB];
   int ct = bx;
   int seg = 0;
@@ -196,7 +208,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
       T fa[4], fb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        fa[q] = sA[buf][wr + q * 16 + li][k];
+        fa[q] = TRANS_A ? sA[buf][k][wr + q * 16 + li] : sA[buf][wr + q * 16 + li][k];
         fb[q] = sB[buf][k][wc + q * 16 + li];
       }
 #pragma unroll
@@ -210,26 +222,36 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
   store_tile<T>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
 }
 
-template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
-  gemm_tile<T, TRANS_A>(g, blockIdx.x, blockIdx.y);
+// Tile order.  The hardware hands workgroup k of a launch to XCD k % 8, and
+// each XCD has its own L2.  The dispatch index is first remapped so that each
+// XCD owns a contiguous range of logical tiles, then the logical tiles are
+// walked in groups of TILE_GROUP tile rows, column by column, so the tiles
+// one XCD runs at the same time share a few A row panels and B column panels
+// instead of touching a new B panel per tile.
+constexpr int NUM_XCD = 8;
+constexpr int TILE_GROUP = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int pid, int total) {
+  const int q = total / NUM_XCD, rem = total % NUM_XCD;
+  const int x = pid % NUM_XCD, loc = pid / NUM_XCD;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + loc;
 }
 
-// Grouped launch: many independent products in one grid.  probs[p] covers
-// tiles [tile_start[p], tile_start[p+1]) in row-major tile order.
+__device__ __forceinline__ void grouped_tile(int L, int ntx, int nty, int& bx, int& by) {
+  const int per = TILE_GROUP * ntx;
+  const int grp = L / per, r0 = grp * TILE_GROUP;
+  const int gs = min(nty - r0, TILE_GROUP), w = L - grp * per;
+  by = r0 + w % gs;
+  bx = w / gs;
+}
+
 template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, 2)
-gemm_grouped(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
-  const int b = blockIdx.x;
-  int lo = 0, hi = nprob - 1;
-  while (lo < hi) {  // last p with tile_start[p] <= b
-    const int mid = (lo + hi + 1) >> 1;
-    if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  const GemmArgs<T>& g = probs[lo];
-  const int local = b - tile_start[lo];
+__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
   const int ntx = g.ntile[0] + g.ntile[1];
-  gemm_tile<T, TRANS_A>(g, local % ntx, local / ntx);
+  const int nty = (g.M + GEMM_TILE - 1) / GEMM_TILE;
+  int bx, by;
+  grouped_tile(xcd_contiguous(blockIdx.x, ntx * nty), ntx, nty, bx, by);
+  gemm_tile<T, TRANS_A>(g, bx, by);
 }
 
 // Host: number of 128 x 128 tiles of a product (fills g.ntile).
@@ -279,7 +301,7 @@ inline hipError_t launch_gemm(const GemmArgs<T>& a0, bool trans_a, hipStream_t s
     total += a.ntile[q];
   }
   if (total == 0) return hipSuccess;
-  dim3 grid(static_cast<unsigned>(total), static_cast<unsigned>((a.M + GEMM_TILE - 1) / GEMM_TILE));
+  dim3 grid(static_cast<unsigned>(total) * static_cast<unsigned>((a.M + GEMM_TILE - 1) / GEMM_TILE));
   ProfScope prof(s, gemm_prof_kind<T>(trans_a), gemm_flops(a), gemm_bytes(a));
   if (trans_a)
     hipLaunchKernelGGL((gemm_lds<T, true>), grid, dim3(256), 0, s, a);
