@@ -83,6 +83,21 @@ struct ProfScope {
   }
 };
 
+// Second stream of the calling host thread on the current device (created on
+// first use, default priority, never destroyed).  `dst` waits for everything
+// enqueued on `src` so far via event ev[k]; an event is re-recorded only
+// after the wait on its previous record has been enqueued.
+struct SideStream {
+  hipStream_t s2;
+  hipEvent_t ev[3];
+};
+hipError_t side_stream(SideStream** out);
+inline hipError_t stream_wait(hipStream_t dst, hipStream_t src, hipEvent_t ev) {
+  hipError_t e = hipEventRecord(ev, src);
+  if (e != hipSuccess) return e;
+  return hipStreamWaitEvent(dst, ev, 0);
+}
+
 // Device status codes raised by kernels (stored in an int32 flag; the
 // smallest (most negative) code wins via atomicMin).
 __device__ inline void raise_status(int* flag, int code) { atomicMin(flag, code); }

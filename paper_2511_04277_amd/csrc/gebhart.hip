@@ -51,12 +51,27 @@ inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
 }
 
 // LDU factorization of K in place; Y (if given, n+1 columns) is eliminated too.
+//
+// Look-ahead: the update of panel p's trailing matrix is split.  Its first
+// 1024 columns (panel p+1) are updated on the caller's stream s, so panel
+// p+1's chain of diagonal inverses and narrow updates can start at once; the
+// rest of the trailing matrix and the right-hand sides are updated on the
+// side stream s2 meanwhile.  Panel p+1's row-block forward substitution waits
+// for that part (event), and the call joins s2 back into s at the end.  The
+// arithmetic and its order per element are the same as without the split.
 template <class T>
 hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc, hipStream_t s) {
   const long ldk = f.ldk;
   T* kf = f.kf;
+  SideStream* ss = nullptr;
+  hipError_t e = side_stream(&ss);
+  if (e != hipSuccess) return e;
+  hipStream_t s2 = ss->s2;
+  e = stream_wait(s2, s, ss->ev[0]);  // s2 starts after the caller's earlier work
+  if (e != hipSuccess) return e;
   for (int c0 = 0; c0 < f.np; c0 += NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
+    const int c2 = std::min(c1 + NB2, f.np);
     // (1) panel: 128-wide blocks; updates stay inside the panel's columns
     for (int k0 = c0; k0 < c1; k0 += NB) {
       T* dk = f.dinv + static_cast<long>(k0) * NB;
@@ -78,6 +93,12 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
         RAD_GEMM(u, false);
       }
     }
+    // the previous panel's far update must be done before this panel's rows
+    // to the right are eliminated
+    if (c0 > 0) {
+      e = stream_wait(s, s2, ss->ev[1]);
+      if (e != hipSuccess) return e;
+    }
     // (2) the panel's rows to the right of the panel: block forward substitution
     for (int k0 = c0; k0 + NB < c1; k0 += NB) {
       const int r1 = k0 + NB;
@@ -88,15 +109,28 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
       if (Y) gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
       if (u.nseg) RAD_GEMM(u, false);
     }
-    // (3) everything below and right of the panel: one K = panel-width GEMM
+    // (3) everything below and right of the panel: K = panel-width GEMMs,
+    // the next panel's columns on s, the rest on s2
     if (c1 < f.np) {
       GemmArgs<T> u = update_args<T>(kf + static_cast<long>(c1) * ldk + c0, ldk, f.np - c1, c1 - c0);
       gemm_add_segment<T>(u, kf + static_cast<long>(c0) * ldk + c1, ldk, kf + static_cast<long>(c1) * ldk + c1,
-                          ldk, f.np - c1);
-      if (Y) gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+                          ldk, c2 - c1);
       RAD_GEMM(u, false);
+      e = stream_wait(s2, s, ss->ev[2]);
+      if (e != hipSuccess) return e;
+      GemmArgs<T> v = update_args<T>(kf + static_cast<long>(c1) * ldk + c0, ldk, f.np - c1, c1 - c0);
+      if (c2 < f.np)
+        gemm_add_segment<T>(v, kf + static_cast<long>(c0) * ldk + c2, ldk, kf + static_cast<long>(c1) * ldk + c2,
+                            ldk, f.np - c2);
+      if (Y) gemm_add_segment<T>(v, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+      if (v.nseg) {
+        hipError_t ge = launch_gemm(v, false, s2);
+        if (ge != hipSuccess) return ge;
+      }
     }
   }
+  e = stream_wait(s, s2, ss->ev[1]);  // join
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

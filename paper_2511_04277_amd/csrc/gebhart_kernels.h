@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) 
 // Diagonal dominance of K makes every pivot order stable, so no pivoting is
 // needed; the scalar pivots are the same Schur-complement diagonals as in
 // unblocked elimination and are checked against the singularity threshold.
-constexpr int GJ_THREADS = 1024;
+constexpr int GJ_WAVES = 4;    // small enough to share a CU with one GEMM tile
+constexpr int GJ_THREADS = 64 * GJ_WAVES;
 
 // 1/x: hardware reciprocal refined by Newton steps to full precision
 __device__ __forceinline__ double recip_nr(double x) {
@@ -187,11 +188,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T>
+template <class T, int NW>
 __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int BT = 16;              // pivot tile
   constexpr int NT = NB / BT;         // 8 tiles per side
+  constexpr int TPW = NT * NT / NW;   // tiles per wave (linear tile id = w * TPW + b)
   constexpr int LC = BT + 2;          // padded row of the column panel
   constexpr int LR = NB + 2;          // padded row of the row panels
   __shared__ T sC[2][NB][LC];         // old tile column s (double-buffered)
@@ -200,35 +202,32 @@ __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __
   __shared__ T sP[BT][BT + 1];        // P^-1, row-major
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int li = l & 15, lg = l >> 4;
-  const int bi = w >> 1, bj0 = (w & 1) * 4;
-  v4 m[4];
+  v4 m[TPW];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < TPW; ++b) {
+    const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      m[b][r] = A[static_cast<long>(bi * BT + Mfma<T>::orow(l, r)) * lda + (bj0 + b) * BT + li];
+      m[b][r] = A[static_cast<long>(bi * BT + Mfma<T>::orow(l, r)) * lda + bj * BT + li];
+  }
   const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
   int singular = 0;
 #pragma unroll 1
   for (int s = 0; s < NT; ++s) {
     const int cb = s & 1;
-    const bool has_col = (s >= bj0) && (s < bj0 + 4);
     // publish the old tile column s and tile row s
-    if (has_col) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (bj0 + b == s)
+    for (int b = 0; b < TPW; ++b) {
+      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
+      if (bj == s)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sC[cb][bi * BT + Mfma<T>::orow(l, r)][li] = m[b][r];
-    }
-    if (bi == s) {
+        for (int r = 0; r < 4; ++r) sC[cb][bi * BT + Mfma<T>::orow(l, r)][li] = m[b][r];
+      if (bi == s)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sRo[Mfma<T>::orow(l, r)][(bj0 + b) * BT + li] = m[b][r];
+        for (int r = 0; r < 4; ++r) sRo[Mfma<T>::orow(l, r)][bj * BT + li] = m[b][r];
     }
     // the owner of the pivot tile inverts it (lane j keeps column j)
-    if (bi == s && has_col) {
+    if (w == (NT + 1) * s / TPW) {
       wave_lds_sync();
       const int j = li;
       T c[BT];
@@ -261,51 +260,48 @@ __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __
     }
     __syncthreads();
     // new tile row s: R(s, j) = P^-1 Ro(s, j), R(s, s) = P^-1
-    if (bi == s) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int jt = bj0 + b;
-        if (jt == s) {
+    for (int b = 0; b < TPW; ++b) {
+      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
+      if (bi != s) continue;
+      if (bj == s) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) m[b][r] = sP[Mfma<T>::orow(l, r)][li];
-        } else {
-          v4 acc = v4{0, 0, 0, 0};
+        for (int r = 0; r < 4; ++r) m[b][r] = sP[Mfma<T>::orow(l, r)][li];
+      } else {
+        v4 acc = v4{0, 0, 0, 0};
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
-            acc = Mfma<T>::mma(sP[li][4 * kk + lg], sRo[4 * kk + lg][jt * BT + li], acc);
-          m[b] = acc;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][jt * BT + li] = m[b][r];
+        for (int kk = 0; kk < 4; ++kk)
+          acc = Mfma<T>::mma(sP[li][4 * kk + lg], sRo[4 * kk + lg][bj * BT + li], acc);
+        m[b] = acc;
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][bj * BT + li] = m[b][r];
     }
     __syncthreads();
     // rank-16 update of the other tile rows; tile column s becomes -M(i,s) P^-1
-    if (bi != s) {
-      T a[4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) a[kk] = -sC[cb][bi * BT + li][4 * kk + lg];
+    for (int b = 0; b < TPW; ++b) {
+      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
+      if (bi == s) continue;
+      if (bj == s) m[b] = v4{0, 0, 0, 0};
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int jt = bj0 + b;
-        if (jt == s) m[b] = v4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) m[b] = Mfma<T>::mma(a[kk], sR[4 * kk + lg][jt * BT + li], m[b]);
-      }
+      for (int kk = 0; kk < 4; ++kk)
+        m[b] = Mfma<T>::mma(-sC[cb][bi * BT + li][4 * kk + lg], sR[4 * kk + lg][bj * BT + li], m[b]);
     }
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < TPW; ++b) {
+    const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      out[(bi * BT + Mfma<T>::orow(l, r)) * NB + (bj0 + b) * BT + li] = m[b][r];
+    for (int r = 0; r < 4; ++r) out[(bi * BT + Mfma<T>::orow(l, r)) * NB + bj * BT + li] = m[b][r];
+  }
   if (singular) raise_status(&sc->status, RAD_ESINGULAR);
 }
 
 template <class T>
 __global__ void __launch_bounds__(GJ_THREADS)
 gj_inverse(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
-  gj_body<T>(A, lda, out, sc);
+  gj_body<T, GJ_WAVES>(A, lda, out, sc);
 }
 
 // many diagonal blocks (of different problems) in one launch
@@ -320,7 +316,7 @@ struct GjJob {
 template <class T>
 __global__ void __launch_bounds__(GJ_THREADS) gj_batched(const GjJob<T>* __restrict__ jobs) {
   const GjJob<T> jb = jobs[blockIdx.x];
-  gj_body<T>(jb.A, jb.lda, jb.out, jb.sc);
+  gj_body<T, GJ_WAVES>(jb.A, jb.lda, jb.out, jb.sc);
 }
 
 // dst (D, rows < n, cols <= n) <- src (S)
