@@ -32,7 +32,7 @@ struct rad_batch_plan {
   void* prepared_for = nullptr;
   // filled by layout()
   struct InstOff { size_t ctrl, scale, inv_area, blkmax, partial; int t; long pairs; };
-  struct ProbOff { int inst, band, n, np; long ldk, ldy, ldx, ldp; size_t kf, dinv, y, x, r, p, sc; };
+  struct ProbOff { int inst, band, n, np, P2; long ldk, ldy, ldx, ldp, ldw, ldt; size_t kf, dinv, y, x, r, p, sc, w, v, scr; };
   std::vector<InstOff> io;
   std::vector<ProbOff> po;
   size_t tables_off = 0;
@@ -47,7 +47,33 @@ struct rad_batch_plan {
 namespace rad {
 namespace {
 
-enum { L_GJ = 0, L_GEMM = 1 };
+enum { L_GJ = 0, L_GEMM = 1, L_COPY = 2, L_TRI_INIT = 3 };
+
+// one row-block copy of a batched launch: rows [0, rows) of src -> dst, cols columns
+template <class T>
+struct CopyJob {
+  const T* src;
+  long lds;
+  T* dst;
+  long ldd;
+  int cols;
+};
+
+template <class T>
+__global__ void __launch_bounds__(256)
+b_copy_jobs(const CopyJob<T>* __restrict__ jobs, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const CopyJob<T> j = jobs[q];
+  const long i = blockIdx.x - start[q];
+  for (int c = threadIdx.x; c < j.cols; c += blockDim.x) j.dst[i * j.ldd + c] = j.src[i * j.lds + c];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+b_tri_init(const TriJob<T>* __restrict__ jobs, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  tri_init_row<T>(jobs[q], static_cast<int>(blockIdx.x - start[q]));
+}
 
 struct ProbDesc {
   const double* F;
@@ -245,6 +271,22 @@ struct Sched {
   T* dinv(int q) { return reinterpret_cast<T*>(base + P->po[q].dinv); }
   T* y(int q) { return reinterpret_cast<T*>(base + P->po[q].y); }
   Scalars* sc(int q) { return reinterpret_cast<Scalars*>(base + P->po[q].sc); }
+  T* w(int q) { return reinterpret_cast<T*>(base + P->po[q].w); }
+  T* v(int q) { return reinterpret_cast<T*>(base + P->po[q].v); }
+  T* scr(int q) { return reinterpret_cast<T*>(base + P->po[q].scr); }
+  TriJob<T> tri_job(int q) {
+    const auto& o = P->po[q];
+    return TriJob<T>{kf(q), o.ldk, dinv(q), o.np, w(q), v(q), o.ldw, scr(q), o.ldt};
+  }
+  void emit_rows(std::vector<rad_batch_plan::Launch>& out, int kind, size_t off, std::vector<long>& rs, int count) {
+    rad_batch_plan::Launch L{};
+    L.kind = kind;
+    L.count = count;
+    L.off = off;
+    L.off2 = tb->add(rs.data(), rs.size());
+    L.grid = static_cast<unsigned>(rs.back());
+    out.push_back(L);
+  }
 
   void emit_gemm(std::vector<rad_batch_plan::Launch>& out, std::vector<GemmArgs<T>>& a, bool trans) {
     if (a.empty()) return;
@@ -380,40 +422,57 @@ struct Sched {
     for (int pan = 0; pan < mp; ++pan) rows_and_outer(P->fwd, pan, false);
   }
 
-  // back substitution, each problem from its own last block down
+  // W_p = U_pp^-1, V_p = L_pp^-1 of every problem's panels (same joins as the
+  // single-model tri_level launches)
+  void panel_inverses() {
+    std::vector<TriJob<T>> jobs;
+    std::vector<long> rs(1, 0);
+    for (int q = 0; q < P->nprob; ++q) {
+      jobs.push_back(tri_job(q));
+      rs.push_back(rs.back() + P->po[q].np);
+    }
+    emit_rows(P->factor, L_TRI_INIT, tb->add(jobs.data(), jobs.size()), rs, P->nprob);
+    std::vector<GemmArgs<T>> g;
+    for (int b = NB; b < NB2; b *= 2)
+      for (int stage = 0; stage < 2; ++stage) {
+        for (int q = 0; q < P->nprob; ++q) {
+          const TriJob<T> j = tri_job(q);
+          for (int p = 0; p < P->po[q].P2; ++p)
+            for (int pr = 0; pr < NB2 / (2 * b); ++pr)
+              for (int mat = 0; mat < 2; ++mat) {
+                GemmArgs<T> a;
+                if (tri_level_args<T>(j, b, stage, p, pr, mat, a)) g.push_back(a);
+              }
+        }
+        emit_gemm(P->factor, g, false);
+      }
+  }
+
+  // back substitution, each problem from its own last panel down:
+  // Y_p <- W_p Y_p (through the scratch), then the rows above the panel
   void back() {
     std::vector<GemmArgs<T>> g;
     const int mp = max_panels();
     for (int rp = 0; rp < mp; ++rp) {
-      for (int kr = 0; kr < NB2 / NB; ++kr) {
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int q = 0; q < P->nprob; ++q) {
-            const auto& o = P->po[q];
-            const int np2 = static_cast<int>(ceil_div(o.np, NB2));
-            const int pan = np2 - 1 - rp;
-            if (pan < 0) continue;
-            const int c0 = pan * NB2, c1 = std::min(c0 + NB2, o.np), k0 = c1 - NB * (kr + 1);
-            if (k0 < c0) continue;
-            if (pass == 0) {  // Y_k = D_k^{-1} Y_k
-              GemmArgs<T> a = gemm_args<T>(dinv(q) + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
-              gemm_add_segment<T>(a, y(q) + static_cast<long>(k0) * o.ldy, o.ldy, y(q) + static_cast<long>(k0) * o.ldy,
-                                  o.ldy, o.n + 1);
-              g.push_back(a);
-            } else if (k0 > c0) {  // rows of the panel above block k
-              GemmArgs<T> a = gemm_args<T>(kf(q) + static_cast<long>(c0) * o.ldk + k0, o.ldk, k0 - c0, NB, T(-1),
-                                           T(1));
-              gemm_add_segment<T>(a, y(q) + static_cast<long>(k0) * o.ldy, o.ldy, y(q) + static_cast<long>(c0) * o.ldy,
-                                  o.ldy, o.n + 1);
-              g.push_back(a);
-            }
-          }
-          emit_gemm(P->back, g, false);
-        }
+      std::vector<CopyJob<T>> cj;
+      std::vector<long> rs(1, 0);
+      for (int q = 0; q < P->nprob; ++q) {
+        const auto& o = P->po[q];
+        const int pan = o.P2 - 1 - rp;
+        if (pan < 0) continue;
+        const int c0 = pan * NB2, L = std::min(c0 + NB2, o.np) - c0;
+        GemmArgs<T> a = gemm_args<T>(w(q) + static_cast<long>(pan) * NB2 * o.ldw, o.ldw, L, L, T(1), T(0));
+        a.tri = 1;
+        gemm_add_segment<T>(a, y(q) + static_cast<long>(c0) * o.ldy, o.ldy, scr(q), o.ldy, o.n + 1);
+        g.push_back(a);
+        cj.push_back(CopyJob<T>{scr(q), o.ldy, y(q) + static_cast<long>(c0) * o.ldy, o.ldy, o.n + 1});
+        rs.push_back(rs.back() + L);
       }
+      emit_gemm(P->back, g, false);
+      if (!cj.empty()) emit_rows(P->back, L_COPY, tb->add(cj.data(), cj.size()), rs, static_cast<int>(cj.size()));
       for (int q = 0; q < P->nprob; ++q) {  // rows above the panel
         const auto& o = P->po[q];
-        const int np2 = static_cast<int>(ceil_div(o.np, NB2));
-        const int pan = np2 - 1 - rp;
+        const int pan = o.P2 - 1 - rp;
         if (pan <= 0) continue;
         const int c0 = pan * NB2, c1 = std::min(c0 + NB2, o.np);
         GemmArgs<T> a = gemm_args<T>(kf(q) + c0, o.ldk, c0, c1 - c0, T(-1), T(1));
@@ -494,6 +553,12 @@ void layout(rad_batch_plan* P) {
       o.dinv = take(static_cast<size_t>(o.np / NB) * NB * NB * es);
       o.y = take(static_cast<size_t>(o.np) * o.ldy * es);
       o.sc = take(sizeof(Scalars));
+      o.P2 = static_cast<int>(ceil_div(o.np, NB2));
+      o.ldw = static_cast<long>(NB2 + 128 / es);
+      o.ldt = tri_ldt(static_cast<long>(128 / es));
+      o.w = take(static_cast<size_t>(o.P2) * NB2 * o.ldw * es);
+      o.v = take(static_cast<size_t>(o.P2) * NB2 * o.ldw * es);
+      o.scr = take(std::max(static_cast<size_t>(NB2) * o.ldy, tri_tmp_elems(o.P2, static_cast<long>(128 / es))) * es);
       if (P->precision == RAD_PREC_FP32_IR) {
         o.x = take(static_cast<size_t>(o.np) * o.ldx * 8);
         o.r = take(static_cast<size_t>(o.np) * o.ldx * 8);
@@ -584,10 +649,12 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
   if (P->precision == RAD_PREC_FP64) {
     Sched<double> sch{P, base, &tb};
     sch.factor();
+    sch.panel_inverses();
     sch.back();
   } else {
     Sched<float> sch{P, base, &tb};
     sch.factor();
+    sch.panel_inverses();
     sch.back();
     sch.forward_only();
     sch.residual();
@@ -597,7 +664,15 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
 template <class T>
 hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const char* tables, hipStream_t s) {
   for (const auto& L : ls) {
-    if (L.kind == L_GJ) {
+    if (L.kind == L_COPY) {
+      hipLaunchKernelGGL(b_copy_jobs<T>, dim3(L.grid), dim3(256), 0, s,
+                         reinterpret_cast<const CopyJob<T>*>(tables + L.off),
+                         reinterpret_cast<const long*>(tables + L.off2), L.count);
+    } else if (L.kind == L_TRI_INIT) {
+      hipLaunchKernelGGL(b_tri_init<T>, dim3(L.grid), dim3(256), 0, s,
+                         reinterpret_cast<const TriJob<T>*>(tables + L.off),
+                         reinterpret_cast<const long*>(tables + L.off2), L.count);
+    } else if (L.kind == L_GJ) {
       ProfScope prof(s, RAD_PROF_DIAG_INVERSE, 2.0 * NB * NB * NB * L.count, 0.0);
       hipLaunchKernelGGL(gj_batched<T>, dim3(L.grid), dim3(GJ_THREADS), 0, s,
                          reinterpret_cast<const GjJob<T>*>(tables + L.off));

@@ -155,23 +155,44 @@ hipError_t forward_only(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s)
   return hipSuccess;
 }
 
-// Y <- U^{-1} Y in place (all np rows; padded rows stay zero).
+// W_p = U_pp^-1 and V_p = L_pp^-1 of every panel (seven launches).
 template <class T>
-hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
+hipError_t panel_inverses(const Fact<T>& f, T* tmp, long ldt, hipStream_t s) {
+  TriJob<T> j{f.kf, f.ldk, f.dinv, f.np, f.W, f.V, f.ldw, tmp, ldt};
+  hipLaunchKernelGGL(tri_init<T>, dim3(f.np), dim3(256), 0, s, j);
+  for (int b = NB; b < NB2; b *= 2)
+    for (int stage = 0; stage < 2; ++stage) {
+      ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32, 0.0, 0.0);
+      hipLaunchKernelGGL(tri_level<T>, dim3(tri_level_blocks(f.P2, b)), dim3(256), 0, s, j, b, stage);
+    }
+  return hipGetLastError();
+}
+
+// Y_p <- op(M_p) Y_p for panel p with a triangular panel inverse M_p, through
+// the scratch S (one panel of right-hand sides)
+template <class T>
+hipError_t apply_panel_inverse(const T* Mp, long ldm, bool trans, int tri, int c0, int L, T* Y, long ldy, int wy,
+                               T* S, long lds, hipStream_t s) {
+  GemmArgs<T> a = gemm_args<T>(Mp, ldm, L, L, T(1), T(0));
+  a.tri = tri;
+  gemm_add_segment<T>(a, Y + static_cast<long>(c0) * ldy, ldy, S, lds, wy);
+  RAD_GEMM(a, trans);
+  hipLaunchKernelGGL(copy_rows<T>, dim3(L), dim3(256), 0, s, S, lds, Y + static_cast<long>(c0) * ldy, ldy, wy);
+  return hipGetLastError();
+}
+
+// Y <- U^{-1} Y in place (all np rows; padded rows stay zero): per panel from
+// the last, Y_p <- W_p Y_p, then the rows above take the panel's contribution
+// in one K = panel-width product.
+template <class T>
+hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* S, long lds, hipStream_t s) {
   const long ldk = f.ldk;
   const int last_c0 = ((f.np - 1) / NB2) * NB2;
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
-    for (int k0 = c1 - NB; k0 >= c0; k0 -= NB) {
-      GemmArgs<T> d = gemm_args<T>(f.dinv + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
-      gemm_add_segment<T>(d, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(k0) * ldy, ldy, wy);
-      RAD_GEMM(d, false);
-      if (k0 > c0) {
-        GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + k0, ldk, k0 - c0, NB);
-        gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(c0) * ldy, ldy, wy);
-        RAD_GEMM(u, false);
-      }
-    }
+    const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    hipError_t e = apply_panel_inverse<T>(Wp, f.ldw, false, 1, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    if (e != hipSuccess) return e;
     if (c0 > 0) {
       GemmArgs<T> u = update_args<T>(f.kf + c0, ldk, c0, c1 - c0);
       gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
@@ -181,39 +202,30 @@ hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
   return hipSuccess;
 }
 
-// Y <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z.
+// Y <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z, panel by panel
+// with the transposed panel inverses.
 template <class T>
-hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, hipStream_t s) {
+hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* S, long lds, hipStream_t s) {
   const long ldk = f.ldk;
-  // U^T Z = Y: forward over blocks
+  // U^T Z = Y: forward over panels (op(W_p) = W_p^T is lower triangular)
   for (int c0 = 0; c0 < f.np; c0 += NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
-    for (int k0 = c0; k0 < c1; k0 += NB) {
-      GemmArgs<T> d = gemm_args<T>(f.dinv + static_cast<long>(k0) * NB, NB, NB, NB, T(1), T(0));
-      gemm_add_segment<T>(d, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(k0) * ldy, ldy, wy);
-      RAD_GEMM(d, true);
-      const int r1 = k0 + NB;
-      if (r1 < c1) {  // rows of the panel below block k: (U_{k, r1..c1})^T Z_k
-        GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(k0) * ldk + r1, ldk, c1 - r1, NB);
-        gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
-        RAD_GEMM(u, true);
-      }
-    }
+    const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    hipError_t e = apply_panel_inverse<T>(Wp, f.ldw, true, 2, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    if (e != hipSuccess) return e;
     if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + c1, ldk, f.np - c1, c1 - c0);
       gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
       RAD_GEMM(u, true);
     }
   }
-  // L^T Lambda = Z: backward over blocks (unit diagonal)
+  // L^T Lambda = Z: backward over panels (op(V_p) = V_p^T is upper triangular)
   const int last_c0 = ((f.np - 1) / NB2) * NB2;
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
-    for (int k0 = c1 - NB; k0 > c0; k0 -= NB) {  // rows of the panel above block k
-      GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(k0) * ldk + c0, ldk, k0 - c0, NB);
-      gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(c0) * ldy, ldy, wy);
-      RAD_GEMM(u, true);
-    }
+    const T* Vp = f.V + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    hipError_t e = apply_panel_inverse<T>(Vp, f.ldw, true, 1, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    if (e != hipSuccess) return e;
     if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk, ldk, c0, c1 - c0);
       gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
@@ -233,6 +245,9 @@ struct GebWork {
   double* p;    // FP64 P = F_sq diag(rho) (np x ldp), refinement only
   long ldp;
   double* part; // grad_eps partial sums (adjoint)
+  void* scr;    // (T) one panel of right-hand sides (NB2 x ldy), shared with
+                // the panel-inverse products (tri_tmp_elems, ld ldt)
+  long ldt;
   size_t bytes;
   bool ok;
 };
@@ -255,6 +270,14 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
     w.p = cv.take<double>(static_cast<size_t>(np) * w.ldp);
   }
   if (adjoint) w.part = cv.take<double>(static_cast<size_t>(ceil_div(n, GE_ROWS) * n));
+  {
+    const size_t es = prec == RAD_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const long pad = static_cast<long>(128 / es);
+    const int P2 = static_cast<int>(ceil_div(np, NB2));
+    w.ldt = tri_ldt(pad);
+    const size_t elems = std::max(static_cast<size_t>(NB2) * w.ldy, tri_tmp_elems(P2, pad));
+    w.scr = cv.take<char>(elems * es);
+  }
   w.bytes = cv.used;
   w.ok = cv.ok;
   return w;
@@ -320,7 +343,8 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     hipLaunchKernelGGL(geb_form<double>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
                        rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
     RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s));
-    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, s));
+    RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
+    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s));
     hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
                        static_cast<long>(ldb));
   } else {
@@ -329,7 +353,8 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     hipLaunchKernelGGL(geb_form<float>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
                        rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
     RAD_HIP_CHECK(factor_forward<float>(f, Y, w.ldy, ni + 1, w.sc, s));
-    RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, s));
+    RAD_HIP_CHECK(panel_inverses<float>(f, static_cast<float*>(w.scr), w.ldt, s));
+    RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
     if (ir_max > 0) {
       zero<double>(w.x, static_cast<long>(f.np) * w.ldx, s);
       zero<double>(w.r, static_cast<long>(f.np) * w.ldx, s);
@@ -344,7 +369,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
         RAD_HIP_CHECK(launch_gemm(a, false, s));
         hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldx, ni, Y, w.ldy, w.sc);
         RAD_HIP_CHECK(forward_only<float>(f, Y, w.ldy, ni + 1, s));
-        RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, s));
+        RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
         hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx, w.sc);
         ++ir_steps;
         int rc = read_scalars(w.sc, &h, s);
@@ -442,14 +467,14 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
     Fact<double> f = make_fact<double>(const_cast<void*>(factors), factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
     hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
-    RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, s));
+    RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s));
     lam = Y;
     ldlam = w.ldy;
   } else {
     Fact<float> f = make_fact<float>(const_cast<void*>(factors), factor_layout<float>(n));
     float* Y = static_cast<float*>(w.y);
     hipLaunchKernelGGL(load_rhs<float>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
-    RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, s));
+    RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
     zero<double>(w.x, static_cast<long>(f.np) * w.ldx, s);
     hipLaunchKernelGGL((copy_block<float, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx);
     if (ir_max > 0) {
@@ -465,7 +490,7 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
       gemm_add_segment<double>(a, w.x, w.ldx, w.r, w.ldx, ni + 1);
       RAD_HIP_CHECK(launch_gemm(a, true, s));
       hipLaunchKernelGGL(residual_to_rhs, dim3(ni), dim3(256), 0, s, w.r, w.ldx, ni, Y, w.ldy, w.sc);
-      RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, s));
+      RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
       hipLaunchKernelGGL(apply_correction, dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx, w.sc);
       ++ir_steps;
       int rc = read_scalars(w.sc, &h, s);

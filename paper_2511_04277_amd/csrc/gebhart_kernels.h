@@ -18,10 +18,15 @@ template <class T>
 constexpr long pad_elems() { return 128 / static_cast<long>(sizeof(T)); }
 
 // ---------------------------------------------------------------- layout ----
+// Factor buffer: K's LDU factors in place (np x ldk), the inverted 128 x 128
+// diagonal blocks, and per 1024-wide panel p the inverses of the panel's
+// diagonal block of U (W_p, upper) and of L (V_p, unit lower), NB2 x ldw each.
 struct FactorLayout {
   int64_t n, np, P;
   long ldk;
-  size_t kf_off, dinv_off, bytes;
+  int P2;
+  long ldw;
+  size_t kf_off, dinv_off, w_off, v_off, bytes;
 };
 
 template <class T>
@@ -31,11 +36,21 @@ FactorLayout factor_layout(int64_t n) {
   f.np = ceil_div(n, NB) * NB;
   f.P = f.np / NB;
   f.ldk = static_cast<long>(f.np + pad_elems<T>());
+  f.P2 = static_cast<int>(ceil_div(f.np, NB2));
+  f.ldw = NB2 + pad_elems<T>();
   f.kf_off = 0;
   f.dinv_off = align_up(static_cast<size_t>(f.np) * f.ldk * sizeof(T), 256);
-  f.bytes = f.dinv_off + align_up(static_cast<size_t>(f.P) * NB * NB * sizeof(T), 256);
+  f.w_off = f.dinv_off + align_up(static_cast<size_t>(f.P) * NB * NB * sizeof(T), 256);
+  const size_t wbytes = align_up(static_cast<size_t>(f.P2) * NB2 * f.ldw * sizeof(T), 256);
+  f.v_off = f.w_off + wbytes;
+  f.bytes = f.v_off + wbytes;
   return f;
 }
+
+// scratch of the panel-inverse products: one b x ldt block per (panel, pair,
+// matrix) at every level (b <= NB2 / 2)
+inline long tri_ldt(long pad) { return NB2 / 2 + pad; }
+inline size_t tri_tmp_elems(int P2, long pad) { return static_cast<size_t>(P2) * NB2 * tri_ldt(pad); }
 
 // right-hand-side buffers: columns padded to a multiple of 128 plus 128 bytes
 inline long rhs_ld(int64_t n, long pad) { return static_cast<long>(ceil_div(n + 1, 128) * 128 + pad); }
@@ -54,6 +69,10 @@ struct Fact {
   long ldk;
   T* dinv;
   int n, np, P;
+  T* W;       // panel inverses of U (P2 x NB2 x ldw)
+  T* V;       // panel inverses of L
+  long ldw;
+  int P2;
 };
 
 template <class T>
@@ -65,6 +84,10 @@ Fact<T> make_fact(void* base, const FactorLayout& l) {
   f.n = static_cast<int>(l.n);
   f.np = static_cast<int>(l.np);
   f.P = static_cast<int>(l.P);
+  f.W = reinterpret_cast<T*>(static_cast<char*>(base) + l.w_off);
+  f.V = reinterpret_cast<T*>(static_cast<char*>(base) + l.v_off);
+  f.ldw = l.ldw;
+  f.P2 = l.P2;
   return f;
 }
 
@@ -317,6 +340,125 @@ template <class T>
 __global__ void __launch_bounds__(GJ_THREADS) gj_batched(const GjJob<T>* __restrict__ jobs) {
   const GjJob<T> jb = jobs[blockIdx.x];
   gj_body<T, GJ_WAVES>(jb.A, jb.lda, jb.out, jb.sc);
+}
+
+// ----------------------------------------------------- panel inverses ---
+// W_p = U_pp^-1 and V_p = L_pp^-1 for every 1024-wide panel p by recursive
+// doubling over its 128-wide diagonal blocks:
+//   [A B; 0 C]^-1 = [A^-1, -A^-1 B C^-1; 0, C^-1],
+//   [I 0; E I]^-1 = [I, 0; -E, I] generalised to [X 0; E Y]^-1 = [X^-1, 0; -Y^-1 E X^-1, Y^-1],
+// starting from W's diagonal blocks D_k^-1 and V's identity blocks.  Level b
+// joins pairs of b-wide inverses; each join is two MFMA products, run for all
+// panels and pairs in one launch per stage.
+template <class T>
+struct TriJob {
+  const T* kf;
+  long ldk;
+  const T* dinv;
+  int np;
+  T* W;
+  T* V;
+  long ldw;
+  T* tmp;      // tri_tmp_elems scratch
+  long ldt;
+};
+
+// W_p = blockdiag(D_k^-1), V_p = I (zero elsewhere, padded columns included);
+// row r of the padded matrix (all panels stacked)
+template <class T>
+__device__ __forceinline__ void tri_init_row(const TriJob<T>& j, int r) {
+  const int p = r / NB2, rl = r % NB2, kb = rl / NB;
+  T* wr = j.W + (static_cast<long>(p) * NB2 + rl) * j.ldw;
+  T* vr = j.V + (static_cast<long>(p) * NB2 + rl) * j.ldw;
+  const T* drow = j.dinv + (static_cast<long>(r / NB) * NB + rl % NB) * NB;
+  for (int c = threadIdx.x; c < j.ldw; c += blockDim.x) {
+    wr[c] = (c / NB == kb && c < NB2) ? drow[c % NB] : T(0);
+    vr[c] = (c == rl) ? T(1) : T(0);
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) tri_init(TriJob<T> j) {
+  tri_init_row<T>(j, blockIdx.x);
+}
+
+// Operands of one join at level b: panel p, pair q, matrix mat (0 W, 1 V),
+// stage 0 (T = U12 W_bot, T = L21 V_top) or 1 (W12 = -W_top T,
+// V21 = -V_bot T).  False when the pair has no bottom half.  Shared by the
+// single-model kernel and the batch planner, so both compute identically.
+template <class T>
+__host__ __device__ inline bool tri_level_args(const TriJob<T>& j, int b, int stage, int p, int q, int mat,
+                                               GemmArgs<T>& g) {
+  const int nq = NB2 / (2 * b);
+  const int c0 = p * NB2;
+  const int L = j.np - c0 < NB2 ? j.np - c0 : NB2;
+  const int o = 2 * b * q;
+  if (o + b >= L) return false;
+  const int bb = L - o - b < b ? L - o - b : b;
+  T* Wp = j.W + static_cast<long>(p) * NB2 * j.ldw;
+  T* Vp = j.V + static_cast<long>(p) * NB2 * j.ldw;
+  T* tq = j.tmp + (static_cast<long>(p * nq + q) * 2 + mat) * b * j.ldt;
+  const long ldw = j.ldw, ldk = j.ldk;
+  g = GemmArgs<T>{};
+  g.nseg = 1;
+  g.beta = T(0);
+  if (mat == 0) {
+    if (stage == 0) {
+      g.A = j.kf + static_cast<long>(c0 + o) * ldk + (c0 + o + b);
+      g.lda = ldk; g.M = b; g.K = bb; g.alpha = T(1);
+      g.B[0] = Wp + static_cast<long>(o + b) * ldw + (o + b); g.ldb[0] = ldw;
+      g.C[0] = tq; g.ldc[0] = j.ldt; g.N[0] = bb;
+    } else {
+      g.A = Wp + static_cast<long>(o) * ldw + o;
+      g.lda = ldw; g.M = b; g.K = b; g.alpha = T(-1);
+      g.B[0] = tq; g.ldb[0] = j.ldt;
+      g.C[0] = Wp + static_cast<long>(o) * ldw + (o + b); g.ldc[0] = ldw; g.N[0] = bb;
+    }
+  } else {
+    if (stage == 0) {
+      g.A = j.kf + static_cast<long>(c0 + o + b) * ldk + (c0 + o);
+      g.lda = ldk; g.M = bb; g.K = b; g.alpha = T(1);
+      g.B[0] = Vp + static_cast<long>(o) * ldw + o; g.ldb[0] = ldw;
+      g.C[0] = tq; g.ldc[0] = j.ldt; g.N[0] = b;
+    } else {
+      g.A = Vp + static_cast<long>(o + b) * ldw + (o + b);
+      g.lda = ldw; g.M = bb; g.K = bb; g.alpha = T(-1);
+      g.B[0] = tq; g.ldb[0] = j.ldt;
+      g.C[0] = Vp + static_cast<long>(o + b) * ldw + o; g.ldc[0] = ldw; g.N[0] = b;
+    }
+  }
+  g.ntile[0] = (g.N[0] + GEMM_TILE - 1) / GEMM_TILE;
+  g.ntile[1] = 0;
+  return true;
+}
+
+// Grid: panels x pairs x 2 matrices x (b/128)^2 tiles.
+template <class T>
+__global__ void __launch_bounds__(256, 2) tri_level(TriJob<T> j, int b, int stage) {
+  const int tpg = (b / NB) * (b / NB);
+  const int nq = NB2 / (2 * b);
+  int blk = blockIdx.x;
+  const int tile = blk % tpg;
+  blk /= tpg;
+  const int mat = blk % 2;
+  blk /= 2;
+  GemmArgs<T> g;
+  if (!tri_level_args<T>(j, b, stage, blk / nq, blk % nq, mat, g)) return;
+  const int ntx = g.ntile[0], nty = (g.M + GEMM_TILE - 1) / GEMM_TILE;
+  if (tile >= ntx * nty) return;
+  gemm_tile<T, false>(g, tile % ntx, tile / ntx);
+}
+
+inline unsigned tri_level_blocks(int P2, int b) {
+  return static_cast<unsigned>(P2) * (NB2 / (2 * b)) * 2 * (b / NB) * (b / NB);
+}
+
+// dst rows [0, rows) <- src, columns < cols (same precision)
+template <class T>
+__global__ void __launch_bounds__(256)
+copy_rows(const T* __restrict__ src, long lds, T* __restrict__ dst, long ldd, int cols) {
+  const long i = blockIdx.x;
+  for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[i * ldd + j] = src[i * lds + j];
 }
 
 // dst (D, rows < n, cols <= n) <- src (S)

@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace rad {
@@ -46,6 +48,8 @@ struct GemmArgs {
   long lda;
   int M, K;
   T alpha, beta;
+  int tri;             // shape of op(A): 0 full, 1 upper (row tile m0 reads k >= m0),
+                       // 2 lower (k < m0 + 128); the skipped entries must be zero
   int nseg;
   int ntile[2];        // 128-wide column tiles per segment
   int N[2];
@@ -194,14 +198,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
     for (int b = 0; b < 4; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
   T ra[E], rb[E];
-  const int nch = (K + KC - 1) / KC;
-  lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, 0, ra, rb);
-  lds_stage_store<T, TRANS_A>(sA[0], sB[0], ra, rb);
+  // K range of this row tile (triangular op(A) skips its zero blocks)
+  const int kbeg = g.tri == 1 ? m0 : 0;
+  const int kend = g.tri == 2 ? min(K, m0 + GEMM_TILE) : K;
+  const int nch = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
+  if (nch > 0) {
+    lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, kbeg, ra, rb);
+    lds_stage_store<T, TRANS_A>(sA[0], sB[0], ra, rb);
+  }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     const bool more = c + 1 < nch;
-    if (more) lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, (c + 1) * KC, ra, rb);
+    if (more) lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, kbeg + (c + 1) * KC, ra, rb);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = lg * (KC / 4) + s;
@@ -280,7 +289,16 @@ template <class T>
 inline double gemm_flops(const GemmArgs<T>& a) {
   double ncols = 0.0;
   for (int q = 0; q < a.nseg; ++q) ncols += a.N[q];
-  return 2.0 * a.M * ncols * a.K;
+  double mk = static_cast<double>(a.M) * a.K;  // multiply-adds per column
+  if (a.tri != 0) {
+    mk = 0.0;
+    for (int m0 = 0; m0 < a.M; m0 += GEMM_TILE) {
+      const int rows = std::min(GEMM_TILE, a.M - m0);
+      const int kb = a.tri == 1 ? m0 : 0, ke = a.tri == 2 ? std::min(a.K, m0 + GEMM_TILE) : a.K;
+      mk += static_cast<double>(rows) * std::max(0, ke - kb);
+    }
+  }
+  return 2.0 * mk * ncols;
 }
 template <class T>
 inline double gemm_bytes(const GemmArgs<T>& a) {
