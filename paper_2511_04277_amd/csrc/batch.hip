@@ -230,11 +230,13 @@ b_apply_correction(const ProbDesc* __restrict__ pd, const long* __restrict__ sta
 template <class T, bool TRANS_A>
 __global__ void __launch_bounds__(256, 2)
 gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
-  // the grid is the tile count or a multiple of 8, so every tile b this
-  // workgroup takes runs on XCD b % 8, as xcd_contiguous assumes
+  // Tiles are taken in list order, so consecutive tiles go to different
+  // XCDs: the problems of a launch differ widely in K, and giving each XCD a
+  // contiguous range (as for one product) would load some XCDs with all the
+  // large problems.
   const int total = tile_start[nprob];
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    const int t = xcd_contiguous(b, total);
+    const int t = b;
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -248,7 +250,7 @@ gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __rest
   }
 }
 
-constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU (a multiple of 8)
+constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU
 
 // ------------------------------------------------------------- host side ---
 struct TableBuilder {
