@@ -39,9 +39,9 @@ struct rad_batch_plan {
   // launch schedule (table offsets relative to the tables block)
   struct Launch { int kind; int trans; unsigned grid; size_t off, off2; int count; double flops, bytes; };
   std::vector<Launch> factor, back, fwd, resid;
-  size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
+  size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_fin = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
   double sweep_bytes = 0.0;  // algorithmic bytes of one sweep over every instance
-  long total_pairs = 0, total_fblk = 0, total_rows = 0, total_nprow = 0, total_nrow = 0;
+  long total_pairs = 0, total_fblk = 0, total_fin = 0, total_rows = 0, total_nprow = 0, total_nrow = 0;
 };
 
 namespace rad {
@@ -582,7 +582,7 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
   P->resid.clear();
   // enforcement instances
   std::vector<EnfInst> ei;
-  std::vector<long> pair_start(1, 0), fblk_start(1, 0), row_start(1, 0);
+  std::vector<long> pair_start(1, 0), fblk_start(1, 0), fin_start(1, 0), row_start(1, 0);
   for (int i = 0; i < P->count; ++i) {
     const rad_instance& s = P->inst[i];
     const auto& o = P->io[i];
@@ -603,15 +603,18 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
     ei.push_back(e);
     pair_start.push_back(pair_start.back() + o.pairs);
     fblk_start.push_back(fblk_start.back() + ceil_div(s.n, 256));
+    fin_start.push_back(fin_start.back() + fin_blocks(s.n));
     row_start.push_back(row_start.back() + s.n);
     P->sweep_bytes += 16.0 * static_cast<double>(s.n) * (s.n + 1);
   }
   P->total_pairs = pair_start.back();
   P->total_fblk = fblk_start.back();
+  P->total_fin = fin_start.back();
   P->total_rows = row_start.back();
   P->off_enf = tb.add(ei.data(), ei.size());
   P->off_pair = tb.add(pair_start.data(), pair_start.size());
   P->off_fblk = tb.add(fblk_start.data(), fblk_start.size());
+  P->off_fin = tb.add(fin_start.data(), fin_start.size());
   P->off_row = tb.add(row_start.data(), row_start.size());
   // solve problems
   std::vector<ProbDesc> pd;
@@ -761,6 +764,7 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
   const EnfInst* ei = reinterpret_cast<const EnfInst*>(tables + P->off_enf);
   const long* pair_start = reinterpret_cast<const long*>(tables + P->off_pair);
   const long* fblk_start = reinterpret_cast<const long*>(tables + P->off_fblk);
+  const long* fin_start = reinterpret_cast<const long*>(tables + P->off_fin);
   const long* row_start = reinterpret_cast<const long*>(tables + P->off_row);
   const ProbDesc* pd = reinterpret_cast<const ProbDesc*>(tables + P->off_pd);
   const long* nprow = reinterpret_cast<const long*>(tables + P->off_nprow);
@@ -779,8 +783,8 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
         hipLaunchKernelGGL(enf_sweep_batched, dim3(static_cast<unsigned>(P->total_pairs)), dim3(ENF_THREADS), 0, s,
                            ei, pair_start, C, it == 0 ? 1 : 0);
       }
-      hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fblk)), dim3(256), 0, s, ei,
-                         fblk_start, C, parity);
+      hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fin)), dim3(256), 0, s, ei,
+                         fin_start, C, parity);
       hipLaunchKernelGGL(enf_decide_batched, dim3(cb), dim3(64), 0, s, ei, C, parity, enforce_tol);
     }
     hipLaunchKernelGGL(enf_apply_scale_batched, dim3(static_cast<unsigned>(P->total_rows)), dim3(256), 0, s, ei,

@@ -107,7 +107,7 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
         hipLaunchKernelGGL(enf_sweep, dim3(static_cast<unsigned>(pairs)), dim3(ENF_THREADS), 0, s, in,
                            it == 0 ? 1 : 0);
       }
-      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, in,
+      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(fin_blocks(n))), dim3(256), 0, s, in,
                          parity);
       hipLaunchKernelGGL(enf_decide, dim3(1), dim3(64), 0, s, l.ctrl, parity, tol);
     }

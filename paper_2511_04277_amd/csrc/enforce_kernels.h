@@ -298,6 +298,11 @@ enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair
   enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);
 }
 
+// Row sums s_i of the (t + 1) partials of each row: 8 lanes per row take
+// every 8th partial, then combine over the lane masks 1, 2, 4 (fixed order).
+constexpr int FIN_LANES = 8;
+constexpr int FIN_ROWS = 256 / FIN_LANES;  // rows per 256-thread block
+
 __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks, int parity) {
   const int n = in.n, t = in.t;
   const double* __restrict__ partial = in.partial;
@@ -306,17 +311,25 @@ __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, in
   const long nblk = in.pairs;
   EnfCtrl* ctrl = in.ctrl;
   if (ctrl->converged || ctrl->status < 0) return;
-  const int i = blk * blockDim.x + threadIdx.x;
+  const int part = threadIdx.x % FIN_LANES;
+  const int i = blk * FIN_ROWS + threadIdx.x / FIN_LANES;
+  double s = 0.0;
+  if (i < n)
+    for (int q = part; q <= t; q += FIN_LANES) s += partial[static_cast<long>(q) * n + i];
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 4);
   double d = 0.0;
   if (i < n) {
-    double s = 0.0;
-    for (int q = 0; q <= t; ++q) s += partial[static_cast<long>(q) * n + i];
-    if (!(s > 0.0)) raise_status(&ctrl->status, RAD_EZEROROW);
-    scale[i] = 1.0 / s;
+    if (part == 0) {
+      if (!(s > 0.0)) raise_status(&ctrl->status, RAD_EZEROROW);
+      scale[i] = 1.0 / s;
+    }
     d = fabs(s - 1.0);
   }
   double rm = 0.0, em = 0.0;
-  for (long b = i; b < nblk; b += static_cast<long>(nblocks) * blockDim.x) {
+  const long tid = static_cast<long>(blk) * blockDim.x + threadIdx.x;
+  for (long b = tid; b < nblk; b += static_cast<long>(nblocks) * blockDim.x) {
     rm = fmax(rm, blkmax[2 * b]);
     em = fmax(em, blkmax[2 * b + 1]);
   }
@@ -332,11 +345,13 @@ __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, in
   }
 }
 
+inline long fin_blocks(int64_t n) { return ceil_div(n, FIN_ROWS); }
+
 __global__ void __launch_bounds__(256) enf_finalize(EnfInst in, int parity) {
   enf_finalize_body(in, blockIdx.x, gridDim.x, parity);
 }
 
-// blocks [blk_start[k], blk_start[k+1]) are the row blocks of instance k
+// blocks [blk_start[k], blk_start[k+1]) are the FIN_ROWS-row blocks of instance k
 __global__ void __launch_bounds__(256)
 enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count, int parity) {
   const int k = find_segment(blk_start, count, blockIdx.x);
