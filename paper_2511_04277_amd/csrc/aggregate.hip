@@ -1,76 +1,105 @@
 // Multi-node aggregation (thesis Sec. 5.2.3, eq. 5.6-5.7; first two rows of
 // eq. 5.28 for one-sided faces) as one read of the sub-face matrix.
 //
-//   csr_build : single workgroup, stable counting sort of the group map into
-//               member lists (each group's members in increasing index order),
-//               so every later sum runs in a fixed order.
+//   csr_rank, csr_offsets, csr_scatter: stable counting sort of the group map
+//               into member lists (each group's members in increasing index
+//               order), so every later sum runs in a fixed order.
 //   agg_reduce: workgroup = (row group G, chunk of 256 column groups H); each
 //               thread owns one output Y_GH and sums w_i X_ij over i in G,
 //               j in H in member order, then divides by W_G.
+#include <algorithm>
+
 #include "common.h"
 
 namespace rad {
 namespace {
 
-constexpr int CSR_THREADS = 1024;
+constexpr int CSR_CHUNK = 1024;   // indices per rank block
 constexpr int AGG_THREADS = 256;
 
-__global__ void __launch_bounds__(CSR_THREADS)
-csr_build(const int* __restrict__ group, int n, int g, int* __restrict__ offs,
-          int* __restrict__ members, int* __restrict__ status) {
-  extern __shared__ int sh[];       // g+1 counters, then a chunk of group ids
-  int* cnt = sh;
-  int* chunk = sh + (g + 1);
-  const int tid = threadIdx.x;
-  for (int q = tid; q <= g; q += blockDim.x) cnt[q] = 0;
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) {
-    int gi = group[i];
-    if (gi < 0 || gi >= g) {
-      atomicMin(status, RAD_EINVAL);
-    } else {
-      atomicAdd(&cnt[gi], 1);
-    }
+// Stable counting sort of the group map in three passes.  (1) One block per
+// chunk of CSR_CHUNK indices: each index's rank among equal ids earlier in
+// its chunk, and the chunk's count per group.  (2) One block: per group, the
+// offset of each chunk's run (chunks in order) and the group offsets (scan
+// over groups).  (3) Scatter: index i goes to
+// offs[g_i] + chunk_off[chunk][g_i] + rank_i, so members appear in
+// increasing index order and every later sum runs in a fixed order.
+__global__ void __launch_bounds__(CSR_CHUNK)
+csr_rank(const int* __restrict__ group, int n, int g, int* __restrict__ rank, int* __restrict__ cnt,
+         int* __restrict__ status) {
+  __shared__ int chunk[CSR_CHUNK];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int i = c * CSR_CHUNK + tid;
+  int gi = i < n ? group[i] : -1;
+  if (i < n && (gi < 0 || gi >= g)) {
+    atomicMin(status, RAD_EINVAL);
+    gi = -1;
   }
+  chunk[tid] = gi;
   __syncthreads();
-  if (tid == 0) {
+  if (gi < 0) return;
+  int r = 0;
+#pragma unroll 8
+  for (int q = 0; q < tid; ++q) r += (chunk[q] == gi);
+  bool last = true;
+  for (int q = tid + 1; q < CSR_CHUNK; ++q)
+    if (chunk[q] == gi) {
+      last = false;
+      break;
+    }
+  rank[i] = r;
+  if (last) cnt[static_cast<long>(c) * g + gi] = r + 1;
+}
+
+// one block: cnt (nch x g, zero where a group is absent from a chunk) becomes
+// the chunk offsets in place; offs[G] = sum of the counts of groups < G
+__global__ void __launch_bounds__(1024)
+csr_offsets(int* __restrict__ cnt, int nch, int g, int* __restrict__ offs, int* __restrict__ status) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  const int per = (g + 1023) / 1024;
+  const int g0 = tid * per, g1 = min(g, g0 + per);
+  int sum = 0;
+  for (int G = g0; G < g1; ++G) {
     int run = 0;
-    for (int q = 0; q < g; ++q) {
-      int c = cnt[q];
-      if (c == 0) atomicMin(status, RAD_EINVAL);
-      offs[q] = run;
-      cnt[q] = run;  // becomes the running insert position
-      run += c;
+    for (int c = 0; c < nch; ++c) {
+      const int v = cnt[static_cast<long>(c) * g + G];
+      cnt[static_cast<long>(c) * g + G] = run;
+      run += v;
+    }
+    if (run == 0) atomicMin(status, RAD_EINVAL);  // empty group
+    offs[G] = run;  // total for now
+    sum += run;
+  }
+  part[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {  // exclusive scan over the 1024 thread totals
+    int run = 0;
+    for (int q = 0; q < 1024; ++q) {
+      const int v = part[q];
+      part[q] = run;
+      run += v;
     }
     offs[g] = run;
   }
   __syncthreads();
-  // stable placement, chunk by chunk in index order
-  for (int base = 0; base < n; base += blockDim.x) {
-    int i = base + tid;
-    int gi = (i < n) ? group[i] : -1;
-    if (gi >= g) gi = -1;
-    chunk[tid] = gi;
-    __syncthreads();
-    if (gi >= 0) {
-      int rank = 0;
-      for (int q = 0; q < tid; ++q) rank += (chunk[q] == gi);
-      members[cnt[gi] + rank] = i;
-    }
-    __syncthreads();
-    if (gi >= 0) {
-      // the last member of this group inside the chunk advances the cursor
-      bool last = true;
-      for (int q = tid + 1; q < blockDim.x; ++q)
-        if (chunk[q] == gi) { last = false; break; }
-      if (last) {
-        int rank = 0;
-        for (int q = 0; q < tid; ++q) rank += (chunk[q] == gi);
-        cnt[gi] += rank + 1;
-      }
-    }
-    __syncthreads();
+  int run = part[tid];
+  for (int G = g0; G < g1; ++G) {
+    const int v = offs[G];
+    offs[G] = run;
+    run += v;
   }
+}
+
+__global__ void __launch_bounds__(256)
+csr_scatter(const int* __restrict__ group, int n, int g, const int* __restrict__ rank,
+            const int* __restrict__ cnt, const int* __restrict__ offs, int* __restrict__ members) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int gi = group[i];
+  if (gi < 0 || gi >= g) return;
+  const int c = i / CSR_CHUNK;
+  members[offs[gi] + cnt[static_cast<long>(c) * g + gi] + rank[i]] = i;
 }
 
 __global__ void __launch_bounds__(AGG_THREADS)
@@ -103,14 +132,19 @@ agg_reduce(const double* __restrict__ X, long ldx, int n, const double* __restri
   if (gw && H == 0) gw[G] = wsum;
 }
 
-__global__ void zero_int(int* p) {
-  if (threadIdx.x == 0) *p = 0;
+__global__ void __launch_bounds__(256) zero_ints(int* __restrict__ p, long count) {
+  for (long q = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; q < count;
+       q += static_cast<long>(gridDim.x) * blockDim.x)
+    p[q] = 0;
 }
 
 struct AggLayout {
   int* status;
   int* offs;
   int* members;
+  int* rank;
+  int* cnt;     // chunks x g
+  int nch;
   size_t bytes;
   bool ok;
 };
@@ -118,9 +152,12 @@ struct AggLayout {
 AggLayout agg_layout(void* work, size_t bytes, int64_t n, int64_t g) {
   Carve cv(work, bytes);
   AggLayout l;
+  l.nch = static_cast<int>(ceil_div(n, CSR_CHUNK));
   l.status = cv.take<int>(1);
   l.offs = cv.take<int>(static_cast<size_t>(g + 1));
   l.members = cv.take<int>(static_cast<size_t>(n));
+  l.rank = cv.take<int>(static_cast<size_t>(n));
+  l.cnt = cv.take<int>(static_cast<size_t>(l.nch) * g);
   l.bytes = cv.used;
   l.ok = cv.ok;
   return l;
@@ -145,17 +182,22 @@ extern "C" int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
   RAD_REQUIRE(g >= 1 && g <= n, RAD_EINVAL, "rad_aggregate_nodes: g must be in [1, n]");
   RAD_REQUIRE(ldx >= n + 1 && ldy >= g + 1, RAD_EINVAL, "rad_aggregate_nodes: ld too small");
   RAD_REQUIRE(X && weight && group && Y, RAD_EINVAL, "rad_aggregate_nodes: NULL pointer");
-  // counters for all groups plus one id per thread must fit in LDS
-  RAD_REQUIRE((g + 1 + CSR_THREADS) * sizeof(int) <= 150 * 1024, RAD_EINVAL,
-              "rad_aggregate_nodes: too many groups for one launch");
+  RAD_REQUIRE(ceil_div(n, CSR_CHUNK) * g <= (int64_t(1) << 31) - 1, RAD_EINVAL,
+              "rad_aggregate_nodes: too many groups for this n");
   AggLayout l = agg_layout(work, work_bytes, n, g);
   RAD_REQUIRE(l.ok && reinterpret_cast<uintptr_t>(work) % 256 == 0, RAD_EWORKSPACE,
               "rad_aggregate_nodes: workspace too small or not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, s, l.status);
-  size_t lds = (g + 1 + CSR_THREADS) * sizeof(int);
-  hipLaunchKernelGGL(csr_build, dim3(1), dim3(CSR_THREADS), lds, s, group, static_cast<int>(n),
-                     static_cast<int>(g), l.offs, l.members, l.status);
+  const int ni = static_cast<int>(n), gi = static_cast<int>(g);
+  const long ncnt = static_cast<long>(l.nch) * g;
+  hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, l.status, 1L);
+  hipLaunchKernelGGL(zero_ints, dim3(static_cast<unsigned>(std::min<long>(ceil_div(ncnt, 256), 4096))), dim3(256), 0,
+                     s, l.cnt, ncnt);
+  hipLaunchKernelGGL(csr_rank, dim3(static_cast<unsigned>(l.nch)), dim3(CSR_CHUNK), 0, s, group, ni, gi, l.rank,
+                     l.cnt, l.status);
+  hipLaunchKernelGGL(csr_offsets, dim3(1), dim3(1024), 0, s, l.cnt, l.nch, gi, l.offs, l.status);
+  hipLaunchKernelGGL(csr_scatter, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, group, ni, gi,
+                     l.rank, l.cnt, l.offs, l.members);
   dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
   {
     ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));

@@ -31,7 +31,7 @@ struct rad_batch_plan {
   size_t work_bytes = 0;
   void* prepared_for = nullptr;
   // filled by layout()
-  struct InstOff { size_t ctrl, scale, inv_area, blkmax, partial; int t; long pairs; };
+  struct InstOff { size_t ctrl, scale, inv_area, blkmax, finred, partial; int t; long pairs; };
   struct ProbOff { int inst, band, n, np, P2; long ldk, ldy, ldx, ldp, ldw, ldt; size_t kf, dinv, y, x, r, p, sc, w, v, scr; };
   std::vector<InstOff> io;
   std::vector<ProbOff> po;
@@ -536,6 +536,7 @@ void layout(rad_batch_plan* P) {
     o.scale = take(n * sizeof(double));
     o.inv_area = take(n * sizeof(double));
     o.blkmax = take(2 * static_cast<size_t>(o.pairs) * sizeof(double));
+    o.finred = take(3 * static_cast<size_t>(fin_blocks(static_cast<int64_t>(n))) * sizeof(double));
     o.partial = take(static_cast<size_t>(o.t + 1) * n * sizeof(double));
     P->io.push_back(o);
   }
@@ -599,6 +600,7 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
     e.scale = reinterpret_cast<double*>(base + o.scale);
     e.partial = reinterpret_cast<double*>(base + o.partial);
     e.blkmax = reinterpret_cast<double*>(base + o.blkmax);
+    e.finred = reinterpret_cast<double*>(base + o.finred);
     e.ctrl = reinterpret_cast<EnfCtrl*>(base + o.ctrl);
     ei.push_back(e);
     pair_start.push_back(pair_start.back() + o.pairs);
@@ -777,15 +779,14 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
     hipLaunchKernelGGL(enf_inv_area_batched, dim3(static_cast<unsigned>(P->total_fblk)), dim3(256), 0, s, ei,
                        fblk_start, C);
     for (int it = 0; it < enforce_iters; ++it) {
-      const int parity = it & 1;
       {
         ProfScope prof(s, RAD_PROF_ENFORCE_SWEEP, 0.0, P->sweep_bytes);
         hipLaunchKernelGGL(enf_sweep_batched, dim3(static_cast<unsigned>(P->total_pairs)), dim3(ENF_THREADS), 0, s,
                            ei, pair_start, C, it == 0 ? 1 : 0);
       }
       hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fin)), dim3(256), 0, s, ei,
-                         fin_start, C, parity);
-      hipLaunchKernelGGL(enf_decide_batched, dim3(cb), dim3(64), 0, s, ei, C, parity, enforce_tol);
+                         fin_start, C);
+      hipLaunchKernelGGL(enf_decide_batched, dim3(static_cast<unsigned>(C)), dim3(256), 0, s, ei, enforce_tol);
     }
     hipLaunchKernelGGL(enf_apply_scale_batched, dim3(static_cast<unsigned>(P->total_rows)), dim3(256), 0, s, ei,
                        row_start, C);

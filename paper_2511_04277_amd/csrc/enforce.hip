@@ -27,6 +27,7 @@ struct EnfLayout {
   double* scale;
   double* inv_area;
   double* blkmax;
+  double* finred;
   double* partial;
   size_t bytes;
   bool ok;
@@ -40,6 +41,7 @@ EnfLayout enf_layout(void* work, size_t work_bytes, int64_t n) {
   l.scale = cv.take<double>(static_cast<size_t>(n));
   l.inv_area = cv.take<double>(static_cast<size_t>(n));
   l.blkmax = cv.take<double>(static_cast<size_t>(t * (t + 1)));
+  l.finred = cv.take<double>(static_cast<size_t>(3 * fin_blocks(n)));
   l.partial = cv.take<double>(static_cast<size_t>((t + 1) * n));
   l.bytes = cv.used;
   l.ok = cv.ok;
@@ -90,6 +92,7 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
   in.scale = l.scale;
   in.partial = l.partial;
   in.blkmax = l.blkmax;
+  in.finred = l.finred;
   in.ctrl = l.ctrl;
   hipLaunchKernelGGL(enf_init, dim3(1), dim3(64), 0, s, l.ctrl);
   hipLaunchKernelGGL(enf_inv_area, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, in);
@@ -101,15 +104,13 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
     int nb = std::min(batch, max_iter - launched);
     for (int k = 0; k < nb; ++k) {
       int it = launched + k;
-      int parity = it & 1;
       {
         ProfScope prof(s, RAD_PROF_ENFORCE_SWEEP, 0.0, 16.0 * static_cast<double>(n) * (n + 1));
         hipLaunchKernelGGL(enf_sweep, dim3(static_cast<unsigned>(pairs)), dim3(ENF_THREADS), 0, s, in,
                            it == 0 ? 1 : 0);
       }
-      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(fin_blocks(n))), dim3(256), 0, s, in,
-                         parity);
-      hipLaunchKernelGGL(enf_decide, dim3(1), dim3(64), 0, s, l.ctrl, parity, tol);
+      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(fin_blocks(n))), dim3(256), 0, s, in);
+      hipLaunchKernelGGL(enf_decide, dim3(1), dim3(256), 0, s, in, tol);
     }
     RAD_HIP_CHECK(hipGetLastError());
     launched += nb;

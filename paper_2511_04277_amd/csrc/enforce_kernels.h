@@ -16,9 +16,6 @@ struct EnfCtrl {
   int converged;     // 1 once the tolerance is met
   int iters;         // iterations executed
   int pad;
-  double defect[2];  // closure defect per iteration parity (atomic max)
-  double recip[2];   // max |eta_ij - eta_ji| per parity (atomic max)
-  double etamax[2];  // max eta per parity (atomic max)
   double last_defect, last_recip;
 };
 
@@ -48,6 +45,7 @@ struct EnfInst {
   double* scale;            // 1 / s_i of the last closure step
   double* partial;          // (t + 1) x n partial row sums
   double* blkmax;           // 2 per tile pair: max |eta_ij - eta_ji|, max eta
+  double* finred;           // 3 per finalize block: closure defect, the two maxima
   EnfCtrl* ctrl;
 };
 
@@ -303,7 +301,7 @@ enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair
 constexpr int FIN_LANES = 8;
 constexpr int FIN_ROWS = 256 / FIN_LANES;  // rows per 256-thread block
 
-__device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks, int parity) {
+__device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks) {
   const int n = in.n, t = in.t;
   const double* __restrict__ partial = in.partial;
   double* __restrict__ scale = in.scale;  // receives 1 / s_i
@@ -333,54 +331,89 @@ __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, in
     rm = fmax(rm, blkmax[2 * b]);
     em = fmax(em, blkmax[2 * b + 1]);
   }
+  // block maxima to finred (the decide kernel reduces the blocks; no atomics)
+  __shared__ double fr[3][4];
   for (int off = 32; off > 0; off >>= 1) {
     d = fmax(d, __shfl_xor(d, off));
     rm = fmax(rm, __shfl_xor(rm, off));
     em = fmax(em, __shfl_xor(em, off));
   }
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomic_max_nonneg(&ctrl->defect[parity], d);
-    atomic_max_nonneg(&ctrl->recip[parity], rm);
-    atomic_max_nonneg(&ctrl->etamax[parity], em);
+    fr[0][w] = d;
+    fr[1][w] = rm;
+    fr[2][w] = em;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 3; ++c) {
+      double x = fr[c][0];
+      for (int q = 1; q < 4; ++q) x = fmax(x, fr[c][q]);
+      in.finred[3 * static_cast<long>(blk) + c] = x;
+    }
   }
 }
 
 inline long fin_blocks(int64_t n) { return ceil_div(n, FIN_ROWS); }
 
-__global__ void __launch_bounds__(256) enf_finalize(EnfInst in, int parity) {
-  enf_finalize_body(in, blockIdx.x, gridDim.x, parity);
+__global__ void __launch_bounds__(256) enf_finalize(EnfInst in) {
+  enf_finalize_body(in, blockIdx.x, gridDim.x);
 }
 
 // blocks [blk_start[k], blk_start[k+1]) are the FIN_ROWS-row blocks of instance k
 __global__ void __launch_bounds__(256)
-enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count, int parity) {
+enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count) {
   const int k = find_segment(blk_start, count, blockIdx.x);
   const int nb = static_cast<int>(blk_start[k + 1] - blk_start[k]);
-  enf_finalize_body(ins[k], static_cast<int>(blockIdx.x - blk_start[k]), nb, parity);
+  enf_finalize_body(ins[k], static_cast<int>(blockIdx.x - blk_start[k]), nb);
 }
 
-__device__ __forceinline__ void enf_decide_body(EnfCtrl* ctrl, int parity, double tol) {
+// Iteration count, closure defect, reciprocity error and the stop flag from
+// the finalize blocks' maxima (one 256-thread block per instance).
+__device__ __forceinline__ void enf_decide_body(const EnfInst& in, double tol) {
+  EnfCtrl* ctrl = in.ctrl;
   if (ctrl->converged || ctrl->status < 0) return;
-  ctrl->iters += 1;
-  double d = ctrl->defect[parity];
-  double e = ctrl->etamax[parity];
-  ctrl->last_defect = d;
-  ctrl->last_recip = e > 0.0 ? ctrl->recip[parity] / e : 0.0;
-  if (tol > 0.0 && d <= tol) ctrl->converged = 1;
-  // clear the other parity for the next iteration
-  int o = parity ^ 1;
-  ctrl->defect[o] = 0.0;
-  ctrl->recip[o] = 0.0;
-  ctrl->etamax[o] = 0.0;
+  const int nf = (in.n + FIN_ROWS - 1) / FIN_ROWS;
+  double d = 0.0, rm = 0.0, em = 0.0;
+  for (int b = threadIdx.x; b < nf; b += blockDim.x) {
+    d = fmax(d, in.finred[3 * b]);
+    rm = fmax(rm, in.finred[3 * b + 1]);
+    em = fmax(em, in.finred[3 * b + 2]);
+  }
+  __shared__ double fr[3][4];
+  for (int off = 32; off > 0; off >>= 1) {
+    d = fmax(d, __shfl_xor(d, off));
+    rm = fmax(rm, __shfl_xor(rm, off));
+    em = fmax(em, __shfl_xor(em, off));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    fr[0][w] = d;
+    fr[1][w] = rm;
+    fr[2][w] = em;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) {
+      d = fmax(d, fr[0][q]);
+      rm = fmax(rm, fr[1][q]);
+      em = fmax(em, fr[2][q]);
+    }
+    d = fmax(d, fr[0][0]);
+    rm = fmax(rm, fr[1][0]);
+    em = fmax(em, fr[2][0]);
+    ctrl->iters += 1;
+    ctrl->last_defect = d;
+    ctrl->last_recip = em > 0.0 ? rm / em : 0.0;
+    if (tol > 0.0 && d <= tol) ctrl->converged = 1;
+  }
 }
 
-__global__ void enf_decide(EnfCtrl* ctrl, int parity, double tol) {
-  if (threadIdx.x == 0) enf_decide_body(ctrl, parity, tol);
-}
+__global__ void __launch_bounds__(256) enf_decide(EnfInst in, double tol) { enf_decide_body(in, tol); }
 
-__global__ void enf_decide_batched(const EnfInst* __restrict__ ins, int count, int parity, double tol) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < count) enf_decide_body(ins[k].ctrl, parity, tol);
+// one block per instance
+__global__ void __launch_bounds__(256) enf_decide_batched(const EnfInst* __restrict__ ins, double tol) {
+  enf_decide_body(ins[blockIdx.x], tol);
 }
 
 __device__ __forceinline__ void enf_apply_scale_body(const EnfInst& in, long row) {
@@ -423,7 +456,6 @@ __device__ __forceinline__ void enf_init_body(EnfCtrl* ctrl) {
     ctrl->converged = 0;
     ctrl->iters = 0;
     ctrl->pad = 0;
-    for (int q = 0; q < 2; ++q) ctrl->defect[q] = ctrl->recip[q] = ctrl->etamax[q] = 0.0;
     ctrl->last_defect = ctrl->last_recip = 0.0;
   }
 }
