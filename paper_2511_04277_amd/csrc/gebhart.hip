@@ -161,10 +161,8 @@ hipError_t panel_inverses(const Fact<T>& f, T* tmp, long ldt, hipStream_t s) {
   TriJob<T> j{f.kf, f.ldk, f.dinv, f.np, f.W, f.V, f.ldw, tmp, ldt};
   hipLaunchKernelGGL(tri_init<T>, dim3(f.np), dim3(256), 0, s, j);
   for (int b = NB; b < NB2; b *= 2)
-    for (int stage = 0; stage < 2; ++stage) {
-      ProfScope prof(s, sizeof(T) == 8 ? RAD_PROF_GEMM_F64 : RAD_PROF_GEMM_F32, 0.0, 0.0);
+    for (int stage = 0; stage < 2; ++stage)
       hipLaunchKernelGGL(tri_level<T>, dim3(tri_level_blocks(f.P2, b)), dim3(256), 0, s, j, b, stage);
-    }
   return hipGetLastError();
 }
 
