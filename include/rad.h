@@ -254,6 +254,30 @@ int32_t rad_batch_stats(const rad_batch_plan* plan, const void* work,
                         rad_stats* out, void* stream);
 void rad_batch_plan_destroy(rad_batch_plan* plan);
 
+/* ---- tuning ------------------------------------------------------------ */
+/*
+ * Process-wide knobs of the kernels (defaults: 0, 0, 1), normally applied by
+ * the binding from the autotuner's table (paper_2511_04277_amd/tuning.json):
+ *   small_tile_below_f64 / _f32: a GEMM with fewer 128 x 128 output tiles
+ *     than this runs with 64 x 64 tiles (more workgroups for narrow or short
+ *     products); 0 keeps 128 x 128 everywhere;
+ *   lookahead: 1 updates the next panel's columns on the caller's stream and
+ *     the rest of the trailing matrix on a second stream during the
+ *     factorization; 0 keeps every update on the caller's stream.
+ * Results do not depend on the knobs beyond rounding of the same operations
+ * in the same order per element (they are bitwise identical).  Not
+ * synchronised: set them while no call is running.
+ */
+typedef struct rad_tuning {
+  int32_t small_tile_below_f64;
+  int32_t small_tile_below_f32;
+  int32_t lookahead;
+  int32_t reserved;
+} rad_tuning;
+
+int32_t rad_tuning_get(rad_tuning* out);
+int32_t rad_tuning_set(const rad_tuning* in);
+
 /* ---- kernel profiling --------------------------------------------------- */
 /*
  * Optional per-launch timing with HIP events, for measuring the hot kernels

@@ -69,6 +69,15 @@ class RadInstance(ctypes.Structure):
     ]
 
 
+class RadTuning(ctypes.Structure):
+    _fields_ = [
+        ("small_tile_below_f64", ctypes.c_int32),
+        ("small_tile_below_f32", ctypes.c_int32),
+        ("lookahead", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate", "gemm_f64_t",
                  "gemm_f32_t"]
 
@@ -109,15 +118,34 @@ SIGNATURES = {
     "rad_batch_run": (_I32, [_P, _P, _D, _I32, _I32, _P]),
     "rad_batch_stats": (_I32, [_P, _P, _STATS, _P]),
     "rad_batch_plan_destroy": (None, [_P]),
+    "rad_tuning_get": (_I32, [ctypes.POINTER(RadTuning)]),
+    "rad_tuning_set": (_I32, [ctypes.POINTER(RadTuning)]),
     "rad_profile_enable": (_I32, [_I32]),
     "rad_profile_read": (_I32, [ctypes.POINTER(RadKernelProfile), _I32]),
 }
 
 _lib = None
+TUNING_PATH = _PKG / "tuning.json"
+
+
+def apply_tuning(chosen: dict) -> None:
+    """Set the library's runtime knobs (rad_tuning_set) from a dict with keys
+    small_tile_below_f64, small_tile_below_f32, lookahead."""
+    t = RadTuning(int(chosen["small_tile_below_f64"]), int(chosen["small_tile_below_f32"]),
+                  int(chosen["lookahead"]), 0)
+    check(lib().rad_tuning_set(ctypes.byref(t)), "rad_tuning_set")
+
+
+def tuning() -> dict:
+    t = RadTuning()
+    check(lib().rad_tuning_get(ctypes.byref(t)), "rad_tuning_get")
+    return {name: getattr(t, name) for name, _ in t._fields_ if name != "reserved"}
 
 
 def lib() -> ctypes.CDLL:
-    """Load librad.so once; raise if it is missing (no fallback path exists)."""
+    """Load librad.so once; raise if it is missing (no fallback path exists).
+    The autotuner's table (tuning.json beside this file), if present, is
+    applied on load."""
     global _lib
     if _lib is None:
         if not LIB_PATH.exists():
@@ -130,6 +158,9 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = l
+        if TUNING_PATH.exists() and os.environ.get("RAD_NO_TUNING") != "1":
+            import json
+            apply_tuning(json.loads(TUNING_PATH.read_text())["chosen"])
     return _lib
 
 

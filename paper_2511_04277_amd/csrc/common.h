@@ -92,6 +92,7 @@ struct SideStream {
   hipEvent_t ev[3];
 };
 hipError_t side_stream(SideStream** out);
+bool lookahead_enabled();  // tuning: split trailing updates over the two streams
 inline hipError_t stream_wait(hipStream_t dst, hipStream_t src, hipEvent_t ev) {
   hipError_t e = hipEventRecord(ev, src);
   if (e != hipSuccess) return e;

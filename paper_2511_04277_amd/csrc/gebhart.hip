@@ -66,7 +66,8 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
   SideStream* ss = nullptr;
   hipError_t e = side_stream(&ss);
   if (e != hipSuccess) return e;
-  hipStream_t s2 = ss->s2;
+  // without look-ahead the far updates stay on s (the event waits are then no-ops)
+  hipStream_t s2 = lookahead_enabled() ? ss->s2 : s;
   e = stream_wait(s2, s, ss->ev[0]);  // s2 starts after the caller's earlier work
   if (e != hipSuccess) return e;
   for (int c0 = 0; c0 < f.np; c0 += NB2) {
@@ -85,6 +86,7 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
       T* x = kf + static_cast<long>(r1) * ldk + k0;
       GemmArgs<T> a = gemm_args<T>(x, ldk, f.np - r1, NB, T(1), T(0));
       gemm_add_segment<T>(a, dk, NB, x, ldk, NB);
+      a.inplace = 1;  // X overwrites the A21 it reads
       RAD_GEMM(a, false);
       if (r1 < c1) {
         GemmArgs<T> u = update_args<T>(x, ldk, f.np - r1, NB);

@@ -48,8 +48,11 @@ struct GemmArgs {
   long lda;
   int M, K;
   T alpha, beta;
-  int tri;             // shape of op(A): 0 full, 1 upper (row tile m0 reads k >= m0),
-                       // 2 lower (k < m0 + 128); the skipped entries must be zero
+  int tri;             // shape of op(A) by 128-blocks: 0 full, 1 block upper (rows of
+                       // block b read k >= 128 b), 2 block lower (k < 128 (b + 1));
+                       // the skipped entries must be zero
+  int inplace;         // 1: C overwrites the rows of op(A) it reads (N <= 128): one
+                       // column tile per row block, so only 128 x 128 tiles are safe
   int nseg;
   int ntile[2];        // 128-wide column tiles per segment
   int N[2];
@@ -59,62 +62,65 @@ struct GemmArgs {
   long ldc[2];
 };
 
-constexpr int GEMM_TILE = 128;
+constexpr int GEMM_TILE = 128;   // tile of the grouped launches and tile counts (ntile)
 
-// C tile epilogue: C = beta C + alpha acc, stores masked to M x N.
-template <class T>
-__device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[4][4], const GemmArgs<T>& g,
+// C tile epilogue: C = beta C + alpha acc, stores masked to M x N.  NBR x NBR
+// MFMA blocks of 16 x 16 per wave.
+template <class T, int NBR>
+__device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[NBR][NBR], const GemmArgs<T>& g,
                                            T* __restrict__ Cm, long ldc, int M, int N, int wr0, int wc0,
                                            int l) {
   const int li = l & 15;
-  const bool full = (wr0 + 64 <= M) && (wc0 + 64 <= N);
+  const bool full = (wr0 + 16 * NBR <= M) && (wc0 + 16 * NBR <= N);
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < NBR; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < NBR; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = wr0 + rb * 16 + Mfma<T>::orow(l, r);
         const int j = wc0 + cb * 16 + li;
         if (full || (i < M && j < N)) {
-          T v = g.alpha * acc[rb][cb][r];
+          // one explicit fused form, so every tile shape rounds alike
           T* p = Cm + static_cast<long>(i) * ldc + j;
-          if (g.beta != T(0)) v += g.beta * *p;
-          *p = v;
+          const T ax = g.alpha * acc[rb][cb][r];
+          *p = g.beta != T(0) ? fma(g.beta, *p, ax) : ax;
         }
       }
 }
 
-// The workgroup stages each 128 x KC slab of op(A) and KC x 128 slab of B
+// The workgroup stages each TS x KC slab of op(A) and KC x TS slab of B
 // once, with 16-byte global loads, into double-buffered LDS; the four waves
-// read their MFMA fragments from LDS.  Within a K chunk, lane group g takes
-// k = g KC/4 + s at MFMA step s.  One barrier per chunk.
+// (2 x 2, each TS/2 x TS/2) read their MFMA fragments from LDS.  Within a K
+// chunk, lane group g takes k = g KC/4 + s at MFMA step s.  One barrier per
+// chunk.  TS = 128 for large products; TS = 64 gives four times the
+// workgroups for narrow or short ones.
 //
 // Operand contract (all operands are the solver's own padded buffers):
 // op(A) is readable for rows < roundup(M, 128) and k < roundup(K, 32), B for
 // rows < roundup(K, 32) and columns < roundup(N, 128); entries with k >= K
 // are zero.  Base pointers and leading dimensions are 16-byte aligned.  Only
 // the stores are masked.
-// K chunk per LDS stage: FP64 uses 16 (2 x 32 KB stages), FP32 32 (2 x 17 KB),
-// so two workgroups share a CU and one's epilogue overlaps the other's MFMAs.
+// K chunk per LDS stage: FP64 uses 16 (2 x 32 KB stages at TS = 128), FP32 32
+// (2 x 17 KB), so two workgroups share a CU and one's epilogue overlaps the
+// other's MFMAs.
 template <class T>
 struct GemmCfg {
   static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
   static constexpr int PA = 2;   // row padding of the A slab (elements)
   static constexpr int PB = 2;   // row padding of the B slab (elements)
-  static constexpr int EPT = KC / 2;  // slab elements per thread per operand
 };
 
-// LDS slab of op(A) for one K chunk: row-major [128][KC] when A is read by
-// rows; K-major [KC][128] when op(A) is a transpose (its global rows are k),
-// so both cases store 16-byte runs without bank conflicts.
-template <class T, bool TRANS_A>
+// LDS slab of op(A) for one K chunk: row-major [TS][KC] when A is read by
+// rows; K-major [KC][TS] when op(A) is a transpose (its global rows are k),
+// so both cases store 16-byte runs.
+template <class T, bool TRANS_A, int TS>
 struct ASlab {
-  static constexpr int R = GEMM_TILE, C = GemmCfg<T>::KC + GemmCfg<T>::PA;
+  static constexpr int R = TS, C = GemmCfg<T>::KC + GemmCfg<T>::PA;
 };
-template <class T>
-struct ASlab<T, true> {
-  static constexpr int R = GemmCfg<T>::KC, C = GEMM_TILE + GemmCfg<T>::PB;
+template <class T, int TS>
+struct ASlab<T, true, TS> {
+  static constexpr int R = GemmCfg<T>::KC, C = TS + GemmCfg<T>::PB;
 };
 
 template <class T, int NE>
@@ -130,30 +136,35 @@ __device__ __forceinline__ void loadv(const T* __restrict__ src, T (&r)[NE]) {
   }
 }
 
-template <class T, bool TRANS_A>
+// elements of each slab per thread
+template <class T, int TS>
+constexpr int slab_ept() { return TS * GemmCfg<T>::KC / 256; }
+
+template <class T, bool TRANS_A, int TS>
 __device__ __forceinline__ void lds_stage_load(const T* __restrict__ A, long lda, const T* __restrict__ Bm,
-                                               long ldb, int m0, int n0, int kc, T (&ra)[GemmCfg<T>::EPT],
-                                               T (&rb)[GemmCfg<T>::EPT]) {
-  constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
-  constexpr int TPR = GEMM_TILE / E;  // threads per 128-wide slab row
+                                               long ldb, int m0, int n0, int kc, T (&ra)[slab_ept<T, TS>()],
+                                               T (&rb)[slab_ept<T, TS>()]) {
+  constexpr int KC = GemmCfg<T>::KC, E = slab_ept<T, TS>();
+  constexpr int TPR = TS / E;   // threads per TS-wide slab row
+  constexpr int TPA = KC / E;   // threads per row of a row-major A slab
   const int t = threadIdx.x;
-  if (!TRANS_A)  // thread -> op(A) row t/2, E consecutive k
-    loadv<T, E>(A + static_cast<long>(m0 + (t >> 1)) * lda + kc + (t & 1) * E, ra);
-  else           // op(A)[m][k] = At[k][m]: thread -> k row t/TPR, E consecutive m
+  if (!TRANS_A)  // thread -> op(A) row t / TPA, E consecutive k
+    loadv<T, E>(A + static_cast<long>(m0 + t / TPA) * lda + kc + (t % TPA) * E, ra);
+  else           // op(A)[m][k] = At[k][m]: thread -> k row t / TPR, E consecutive m
     loadv<T, E>(A + static_cast<long>(kc + t / TPR) * lda + m0 + (t % TPR) * E, ra);
   loadv<T, E>(Bm + static_cast<long>(kc + t / TPR) * ldb + n0 + (t % TPR) * E, rb);
-  (void)KC;
 }
 
-template <class T, bool TRANS_A>
-__device__ __forceinline__ void lds_stage_store(T (*sA)[(ASlab<T, TRANS_A>::C)],
-                                                T (*sB)[GEMM_TILE + GemmCfg<T>::PB],
-                                                const T (&ra)[GemmCfg<T>::EPT], const T (&rb)[GemmCfg<T>::EPT]) {
-  constexpr int E = GemmCfg<T>::EPT;
-  constexpr int TPR = GEMM_TILE / E;
+template <class T, bool TRANS_A, int TS>
+__device__ __forceinline__ void lds_stage_store(T (*sA)[(ASlab<T, TRANS_A, TS>::C)],
+                                                T (*sB)[TS + GemmCfg<T>::PB],
+                                                const T (&ra)[slab_ept<T, TS>()], const T (&rb)[slab_ept<T, TS>()]) {
+  constexpr int KC = GemmCfg<T>::KC, E = slab_ept<T, TS>();
+  constexpr int TPR = TS / E;
+  constexpr int TPA = KC / E;
   const int t = threadIdx.x;
   if (!TRANS_A) {
-    const int m = t >> 1, k0 = (t & 1) * E;
+    const int m = t / TPA, k0 = (t % TPA) * E;
 #pragma unroll
     for (int q = 0; q < E; ++q) sA[m][k0 + q] = ra[q];
   } else {
@@ -166,19 +177,21 @@ __device__ __forceinline__ void lds_stage_store(T (*sA)[(ASlab<T, TRANS_A>::C)],
   for (int q = 0; q < E; ++q) sB[k][nb + q] = rb[q];
 }
 
-// One 128 x 128 output tile: column-tile index bx (over both segments),
+// One TS x TS output tile: column-tile index bx (over both segments),
 // row-tile index by.
-template <class T, bool TRANS_A>
+template <class T, bool TRANS_A, int TS = GEMM_TILE>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int KC = GemmCfg<T>::KC, E = GemmCfg<T>::EPT;
-  __shared__ T sA[2][ASlab<T, TRANS_A>::R][ASlab<T, TRANS_A>::C];
-  __shared__ T sB[2][KC][GEMM_TILE + GemmCfg<T>::PB];
+  constexpr int KC = GemmCfg<T>::KC, E = slab_ept<T, TS>();
+  constexpr int NBR = TS / 32;   // 16 x 16 blocks per wave side
+  __shared__ T sA[2][ASlab<T, TRANS_A, TS>::R][ASlab<T, TRANS_A, TS>::C];
+  __shared__ T sB[2][KC][TS + GemmCfg<T>::PB];
+  const int nt0 = (g.nseg > 0 && g.N[0] > 0) ? (g.N[0] + TS - 1) / TS : 0;
   int ct = bx;
   int seg = 0;
-  if (ct >= g.ntile[0]) {
+  if (ct >= nt0) {
     seg = 1;
-    ct -= g.ntile[0];
+    ct -= nt0;
   }
   const T* __restrict__ Bm = g.B[seg];
   T* __restrict__ Cm = g.C[seg];
@@ -186,49 +199,51 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
   const T* __restrict__ A = g.A;
   const long lda = g.lda;
   const int N = g.N[seg], M = g.M, K = g.K;
-  const int m0 = by * GEMM_TILE, n0 = ct * GEMM_TILE;
+  const int m0 = by * TS, n0 = ct * TS;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int li = l & 15, lg = l >> 4;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 1) * (TS / 2), wc = (wave & 1) * (TS / 2);
 
-  v4 acc[4][4];
+  v4 acc[NBR][NBR];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NBR; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    for (int b = 0; b < NBR; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
   T ra[E], rb[E];
-  // K range of this row tile (triangular op(A) skips its zero blocks)
-  const int kbeg = g.tri == 1 ? m0 : 0;
-  const int kend = g.tri == 2 ? min(K, m0 + GEMM_TILE) : K;
+  // K range of this row tile: a triangular op(A) is zero by 128-blocks, so
+  // the row tile skips the blocks left (upper) or right (lower) of its block
+  const int mb = (m0 / GEMM_TILE) * GEMM_TILE;
+  const int kbeg = g.tri == 1 ? mb : 0;
+  const int kend = g.tri == 2 ? min(K, mb + GEMM_TILE) : K;
   const int nch = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
   if (nch > 0) {
-    lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, kbeg, ra, rb);
-    lds_stage_store<T, TRANS_A>(sA[0], sB[0], ra, rb);
+    lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg, ra, rb);
+    lds_stage_store<T, TRANS_A, TS>(sA[0], sB[0], ra, rb);
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     const bool more = c + 1 < nch;
-    if (more) lds_stage_load<T, TRANS_A>(A, lda, Bm, ldb, m0, n0, kbeg + (c + 1) * KC, ra, rb);
+    if (more) lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg + (c + 1) * KC, ra, rb);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = lg * (KC / 4) + s;
-      T fa[4], fb[4];
+      T fa[NBR], fb[NBR];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NBR; ++q) {
         fa[q] = TRANS_A ? sA[buf][k][wr + q * 16 + li] : sA[buf][wr + q * 16 + li][k];
         fb[q] = sB[buf][k][wc + q * 16 + li];
       }
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < NBR; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = Mfma<T>::mma(fa[x], fb[y], acc[x][y]);
+        for (int y = 0; y < NBR; ++y) acc[x][y] = Mfma<T>::mma(fa[x], fb[y], acc[x][y]);
     }
-    if (more) lds_stage_store<T, TRANS_A>(sA[buf ^ 1], sB[buf ^ 1], ra, rb);
+    if (more) lds_stage_store<T, TRANS_A, TS>(sA[buf ^ 1], sB[buf ^ 1], ra, rb);
     __syncthreads();
   }
-  store_tile<T>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
+  store_tile<T, NBR>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
 }
 
 // Tile order.  The hardware hands workgroup k of a launch to XCD k % 8, and
@@ -254,14 +269,31 @@ __device__ __forceinline__ void grouped_tile(int L, int ntx, int nty, int& bx, i
   bx = w / gs;
 }
 
-template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, 2) gemm_lds(GemmArgs<T> g) {
-  const int ntx = g.ntile[0] + g.ntile[1];
-  const int nty = (g.M + GEMM_TILE - 1) / GEMM_TILE;
+template <class T, int TS>
+inline int tiles_x(const GemmArgs<T>& g) {
+  int t = 0;
+  for (int q = 0; q < g.nseg; ++q) t += g.N[q] > 0 ? (g.N[q] + TS - 1) / TS : 0;
+  return t;
+}
+
+template <class T, bool TRANS_A, int TS>
+__global__ void __launch_bounds__(256, TS == GEMM_TILE ? 2 : 4) gemm_lds(GemmArgs<T> g) {
+  const int nt0 = (g.nseg > 0 && g.N[0] > 0) ? (g.N[0] + TS - 1) / TS : 0;
+  const int nt1 = (g.nseg > 1 && g.N[1] > 0) ? (g.N[1] + TS - 1) / TS : 0;
+  const int ntx = nt0 + nt1;
+  const int nty = (g.M + TS - 1) / TS;
   int bx, by;
   grouped_tile(xcd_contiguous(blockIdx.x, ntx * nty), ntx, nty, bx, by);
-  gemm_tile<T, TRANS_A>(g, bx, by);
+  gemm_tile<T, TRANS_A, TS>(g, bx, by);
 }
+
+// Runtime choice of the tile: a product with fewer than small_tile_below
+// 128 x 128 tiles (precision index 0 = FP64, 1 = FP32) runs with 64 x 64
+// tiles.  Set by rad_tuning_set (tuning.cpp), chosen by the autotuner.
+struct GemmTuning {
+  int small_tile_below[2];
+};
+GemmTuning& gemm_tuning();
 
 // Host: number of 128 x 128 tiles of a product (fills g.ntile).
 template <class T>
@@ -313,18 +345,23 @@ template <class T>
 inline hipError_t launch_gemm(const GemmArgs<T>& a0, bool trans_a, hipStream_t s) {
   GemmArgs<T> a = a0;
   if (a.M <= 0 || a.K <= 0) return hipSuccess;
-  int total = 0;
-  for (int q = 0; q < 2; ++q) {
-    a.ntile[q] = (q < a.nseg && a.N[q] > 0) ? (a.N[q] + GEMM_TILE - 1) / GEMM_TILE : 0;
-    total += a.ntile[q];
-  }
-  if (total == 0) return hipSuccess;
-  dim3 grid(static_cast<unsigned>(total) * static_cast<unsigned>((a.M + GEMM_TILE - 1) / GEMM_TILE));
+  const int big = gemm_tiles<T>(a);
+  if (big == 0) return hipSuccess;
   ProfScope prof(s, gemm_prof_kind<T>(trans_a), gemm_flops(a), gemm_bytes(a));
-  if (trans_a)
-    hipLaunchKernelGGL((gemm_lds<T, true>), grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((gemm_lds<T, false>), grid, dim3(256), 0, s, a);
+  const bool small = !a.inplace && big < gemm_tuning().small_tile_below[sizeof(T) == 8 ? 0 : 1];
+  if (small) {
+    const unsigned grid = static_cast<unsigned>(tiles_x<T, 64>(a)) * static_cast<unsigned>((a.M + 63) / 64);
+    if (trans_a)
+      hipLaunchKernelGGL((gemm_lds<T, true, 64>), dim3(grid), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_lds<T, false, 64>), dim3(grid), dim3(256), 0, s, a);
+  } else {
+    const unsigned grid = static_cast<unsigned>(big);
+    if (trans_a)
+      hipLaunchKernelGGL((gemm_lds<T, true, GEMM_TILE>), dim3(grid), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_lds<T, false, GEMM_TILE>), dim3(grid), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -42,3 +42,18 @@ def test_host_side_argument_errors_need_no_gpu():
     code = lib.rad_enforce_vf(_lib.ctypes.c_void_p(256), 10, 5, _lib.ctypes.c_void_p(256), None, 1, 0.0, 1,
                               None, 0, None, None)
     assert code == _lib.RAD_EINVAL and b"ldf" in lib.rad_last_error()
+
+
+def test_tuning_roundtrip_and_validation():
+    lib = _lib.lib()
+    saved = _lib.tuning()
+    try:
+        _lib.apply_tuning({"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0})
+        assert _lib.tuning() == {"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0}
+        bad = _lib.RadTuning(-1, 0, 1, 0)
+        assert lib.rad_tuning_set(_lib.ctypes.byref(bad)) == _lib.RAD_EINVAL
+        bad = _lib.RadTuning(0, 0, 2, 0)
+        assert lib.rad_tuning_set(_lib.ctypes.byref(bad)) == _lib.RAD_EINVAL
+        assert _lib.tuning()["small_tile_below_f64"] == 300  # unchanged by a rejected call
+    finally:
+        _lib.apply_tuning(saved)

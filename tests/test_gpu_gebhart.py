@@ -164,3 +164,29 @@ def test_full_size_open_box_n16384_sampled_columns():
         assert chk[0] < lim and chk[1] < 10 * lim * scale
         del bd
         torch.cuda.empty_cache()
+
+
+def test_tuning_knobs_leave_results_bitwise_unchanged():
+    """Tile shape and look-ahead reorder launches only: B and the adjoint's
+    gradients must be identical under every setting."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    from paper_2511_04277_amd import _lib as L
+    inst = W.box_with_n(2300, seed=8)
+    fd, eps, rho = dev(inst.f_noisy), dev(inst.eps[0]), dev(inst.rho[0])
+    g = dev(np.random.default_rng(3).standard_normal((inst.n, inst.n + 1)))
+    saved = L.tuning()
+    outs = []
+    try:
+        for tile, look in ((0, 1), (4096, 1), (1 << 30, 0), (256, 0)):
+            L.apply_tuning({"small_tile_below_f64": tile, "small_tile_below_f32": tile, "lookahead": look})
+            for prec in ("fp64", "fp32_ir"):
+                b, fac, _ = rad.gebhart_ref(fd, eps, rho, precision=prec, ir_tol=1e-13, ir_max=3)
+                ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, fd, rho, b, g)
+                outs.append((tile, look, prec, b.clone(), ge.clone(), gr.clone()))
+    finally:
+        L.apply_tuning(saved)
+    for prec in ("fp64", "fp32_ir"):
+        ref = [o for o in outs if o[2] == prec]
+        for o in ref[1:]:
+            assert torch.equal(o[3], ref[0][3]) and torch.equal(o[4], ref[0][4]) and torch.equal(o[5], ref[0][5]), o[:3]
