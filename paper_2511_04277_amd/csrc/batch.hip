@@ -37,7 +37,7 @@ struct rad_batch_plan {
   std::vector<ProbOff> po;
   size_t tables_off = 0;
   // launch schedule (table offsets relative to the tables block)
-  struct Launch { int kind; int trans; unsigned grid; size_t off, off2; int count; double flops, bytes; };
+  struct Launch { int kind; int trans; int ts; unsigned grid; size_t off, off2; int count; double flops, bytes; };
   std::vector<Launch> factor, back, fwd, resid;
   size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_fin = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
   double sweep_bytes = 0.0;  // algorithmic bytes of one sweep over every instance
@@ -226,9 +226,10 @@ b_apply_correction(const ProbDesc* __restrict__ pd, const long* __restrict__ sta
   block_max(m, &d.sc->max_d);
 }
 
-// persistent grouped GEMM: workgroups walk the concatenated tile list
-template <class T, bool TRANS_A>
-__global__ void __launch_bounds__(256, 2)
+// persistent grouped GEMM: workgroups walk the concatenated tile list of
+// TS x TS tiles
+template <class T, bool TRANS_A, int TS>
+__global__ void __launch_bounds__(256, TS == GEMM_TILE ? 2 : 4)
 gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
   // Tiles are taken in list order, so consecutive tiles go to different
   // XCDs: the problems of a launch differ widely in K, and giving each XCD a
@@ -243,14 +244,16 @@ gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __rest
       if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
     }
     const GemmArgs<T>& g = probs[lo];
-    const int ntx = g.ntile[0] + g.ntile[1];
+    int ntx = 0;
+    for (int q = 0; q < g.nseg; ++q) ntx += g.N[q] > 0 ? (g.N[q] + TS - 1) / TS : 0;
     int bx, by;
-    grouped_tile(t - tile_start[lo], ntx, (g.M + GEMM_TILE - 1) / GEMM_TILE, bx, by);
-    gemm_tile<T, TRANS_A>(g, bx, by);
+    grouped_tile(t - tile_start[lo], ntx, (g.M + TS - 1) / TS, bx, by);
+    gemm_tile<T, TRANS_A, TS>(g, bx, by);
   }
 }
 
-constexpr unsigned PERSISTENT_GRID = 2 * 256;  // two resident tiles per CU
+// resident workgroups: two 128-tiles or four 64-tiles per CU
+inline unsigned persistent_grid(int ts) { return ts == GEMM_TILE ? 2 * 256 : 4 * 256; }
 
 // ------------------------------------------------------------- host side ---
 struct TableBuilder {
@@ -263,6 +266,46 @@ struct TableBuilder {
     return off;
   }
 };
+
+// One grouped GEMM launch over the products a (cleared).  The tile follows
+// the same tuning rule as single products: 64 x 64 below the threshold of
+// 128 x 128 tiles, unless a product is in place.  False if there is no work.
+template <class U>
+bool gemm_launch(TableBuilder* tb, std::vector<GemmArgs<U>>& a, bool trans, rad_batch_plan::Launch& L) {
+  int t128 = 0;
+  bool inplace = false;
+  double flops = 0.0, bytes = 0.0;
+  for (auto& g : a) {
+    t128 += gemm_tiles<U>(g);
+    inplace = inplace || g.inplace;
+    flops += gemm_flops(g);
+    bytes += gemm_bytes(g);
+  }
+  if (t128 == 0) {
+    a.clear();
+    return false;
+  }
+  const int ts = (!inplace && t128 < gemm_tuning().small_tile_below[sizeof(U) == 8 ? 0 : 1]) ? 64 : GEMM_TILE;
+  std::vector<int> st(a.size() + 1, 0);
+  for (size_t k = 0; k < a.size(); ++k) {
+    const GemmArgs<U>& g = a[k];
+    const int n = (g.M <= 0 || g.K <= 0) ? 0
+                  : (ts == GEMM_TILE ? gemm_tiles<U>(a[k]) : tiles_x<U, 64>(g) * ((g.M + 63) / 64));
+    st[k + 1] = st[k] + n;
+  }
+  L = rad_batch_plan::Launch{};
+  L.kind = L_GEMM;
+  L.trans = trans ? 1 : 0;
+  L.ts = ts;
+  L.flops = flops;
+  L.bytes = bytes;
+  L.count = static_cast<int>(a.size());
+  L.off = tb->add(a.data(), a.size());
+  L.off2 = tb->add(st.data(), st.size());
+  L.grid = std::min<unsigned>(static_cast<unsigned>(st.back()), persistent_grid(ts));
+  a.clear();
+  return true;
+}
 
 template <class T>
 struct Sched {
@@ -291,29 +334,8 @@ struct Sched {
   }
 
   void emit_gemm(std::vector<rad_batch_plan::Launch>& out, std::vector<GemmArgs<T>>& a, bool trans) {
-    if (a.empty()) return;
-    std::vector<int> ts(a.size() + 1, 0);
-    double flops = 0.0, bytes = 0.0;
-    for (size_t k = 0; k < a.size(); ++k) {
-      ts[k + 1] = ts[k] + gemm_tiles<T>(a[k]);
-      flops += gemm_flops(a[k]);
-      bytes += gemm_bytes(a[k]);
-    }
-    if (ts.back() == 0) {
-      a.clear();
-      return;
-    }
-    rad_batch_plan::Launch L{};
-    L.flops = flops;
-    L.bytes = bytes;
-    L.kind = L_GEMM;
-    L.trans = trans ? 1 : 0;
-    L.count = static_cast<int>(a.size());
-    L.off = tb->add(a.data(), a.size());
-    L.off2 = tb->add(ts.data(), ts.size());
-    L.grid = static_cast<unsigned>(std::min<int>(ts.back(), PERSISTENT_GRID));
-    out.push_back(L);
-    a.clear();
+    rad_batch_plan::Launch L;
+    if (gemm_launch<T>(tb, a, trans, L)) out.push_back(L);
   }
   void emit_gj(std::vector<rad_batch_plan::Launch>& out, std::vector<GjJob<T>>& j) {
     if (j.empty()) return;
@@ -358,6 +380,7 @@ struct Sched {
           T* x = kf(q) + static_cast<long>(r1) * o.ldk + k0;
           GemmArgs<T> a = gemm_args<T>(x, o.ldk, o.np - r1, NB, T(1), T(0));
           gemm_add_segment<T>(a, dinv(q) + static_cast<long>(k0) * NB, NB, x, o.ldk, NB);
+          a.inplace = 1;  // X overwrites the A21 it reads
           g.push_back(a);
         }
         emit_gemm(P->factor, g, false);
@@ -496,21 +519,8 @@ struct Sched {
       gemm_add_segment<double>(a, x, o.ldx, r, o.ldx, o.n + 1);
       g.push_back(a);
     }
-    std::vector<int> ts(g.size() + 1, 0);
-    double flops = 0.0, bytes = 0.0;
-    for (size_t k = 0; k < g.size(); ++k) {
-      ts[k + 1] = ts[k] + gemm_tiles<double>(g[k]);
-      flops += gemm_flops(g[k]);
-      bytes += gemm_bytes(g[k]);
-    }
-    rad_batch_plan::Launch L{};
-    L.flops = flops;
-    L.bytes = bytes;
-    L.kind = L_GEMM;
-    L.count = static_cast<int>(g.size());
-    L.off = tb->add(g.data(), g.size());
-    L.off2 = tb->add(ts.data(), ts.size());
-    L.grid = static_cast<unsigned>(std::min<int>(ts.back(), PERSISTENT_GRID));
+    rad_batch_plan::Launch L;
+    if (!gemm_launch<double>(tb, g, false, L)) return;
     P->resid.push_back(L);
   }
 };
@@ -687,10 +697,20 @@ hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const cha
       ProfScope prof(s, gemm_prof_kind<T>(L.trans != 0), L.flops, L.bytes);
       const GemmArgs<T>* a = reinterpret_cast<const GemmArgs<T>*>(tables + L.off);
       const int* ts = reinterpret_cast<const int*>(tables + L.off2);
-      if (L.trans)
-        hipLaunchKernelGGL((gemm_grouped_persistent<T, true>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
-      else
-        hipLaunchKernelGGL((gemm_grouped_persistent<T, false>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
+      if (L.ts == GEMM_TILE) {
+        if (L.trans)
+          hipLaunchKernelGGL((gemm_grouped_persistent<T, true, GEMM_TILE>), dim3(L.grid), dim3(256), 0, s, a, ts,
+                             L.count);
+        else
+          hipLaunchKernelGGL((gemm_grouped_persistent<T, false, GEMM_TILE>), dim3(L.grid), dim3(256), 0, s, a, ts,
+                             L.count);
+      } else {
+        if (L.trans)
+          hipLaunchKernelGGL((gemm_grouped_persistent<T, true, 64>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
+        else
+          hipLaunchKernelGGL((gemm_grouped_persistent<T, false, 64>), dim3(L.grid), dim3(256), 0, s, a, ts,
+                             L.count);
+      }
     }
   }
   return hipGetLastError();
