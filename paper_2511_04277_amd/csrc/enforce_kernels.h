@@ -9,7 +9,10 @@ namespace {
 
 constexpr int ET = 64;          // tile edge (doubles)
 constexpr int ETP = ET + 1;     // padded LDS row (conflict-free transpose)
-constexpr int ENF_THREADS = 256;
+// 8 waves of 8 tile rows each: at 4 waves per SIMD (two workgroups per
+// CU) the sweep keeps twice the loads in flight of a 4-wave shape
+constexpr int ENF_THREADS = 512;
+constexpr int ENW = ENF_THREADS / 64;  // waves per sweep workgroup
 
 struct EnfCtrl {
   int status;        // device-raised status (0 ok, negative error)
@@ -49,7 +52,7 @@ struct EnfInst {
   EnfCtrl* ctrl;
 };
 
-constexpr int ERW = ET / (ENF_THREADS / 64);  // 16 tile rows per wave
+constexpr int ERW = ET / ENW;  // tile rows per wave
 
 // Element col of a row whose base pointer is wave-uniform: the byte offset
 // is a 32-bit lane value, so loads and stores take the scalar-base form and
@@ -84,12 +87,12 @@ __device__ __forceinline__ double kappa_c(double fij, double fji, double ci, dou
 }
 
 // One workgroup per tile pair (I, J), I <= J, of 64 x 64 tiles.  Lane l of
-// wave w holds column l of tile rows w, w + 4, ..., w + 60, so every load and
+// wave w holds column l of tile rows w, w + ENW, ..., so every load and
 // store instruction of a wave moves one contiguous 512-byte tile row.  The
 // partner tile (J, I) is staged through LDS (65-double rows), where each
 // unordered pair {i, j} meets its mirror; the previous iteration's closure
 // scale 1 / s_i is applied on load.  The thread that updates pair (i, j)
-// also produces the partner's entry (j, i), and its 16 pairs all lie in one
+// also produces the partner's entry (j, i), and its ERW pairs all lie in one
 // partner row, so the partner's row sums are formed in registers; the own
 // tile's rows are summed after a transpose through the same LDS buffer.
 // All sums run in a fixed order (bitwise reproducible).  DIAG: I == J (each
@@ -124,19 +127,19 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     rowc[4][tid - ET] = first ? 1.0 : inv_scale[jr];
   }
   __syncthreads();
-  // own tile (I, J): a[k] = F(r0 + w + 4k, c0 + l).  Row pointers are
+  // own tile (I, J): a[k] = F(r0 + w + ENW k, c0 + l).  Row pointers are
   // wave-uniform and the lane adds its column, so loads use a scalar base.
   const int jg = c0 + l;
   const int jgc = (EDGE && jg >= n) ? n - 1 : jg;
   double a[ERW];
 #pragma unroll
   for (int k = 0; k < ERW; ++k) {
-    const int i = r0 + w + 4 * k;
+    const int i = r0 + w + ENW * k;
     const int ic = (EDGE && i >= n) ? n - 1 : i;
     double v = row_ld(F + static_cast<long>(ic) * ldf, jgc);
     if (EDGE && !(i < n && jg < n)) v = 0.0;
     bad |= !(v >= 0.0) || !(v <= 1.0e300);
-    a[k] = v * rowc[3][w + 4 * k];
+    a[k] = v * rowc[3][w + ENW * k];
   }
   // partner tile (J, I) into LDS: sB[jl][il] = F(c0 + jl, r0 + il)
   if (!DIAG) {
@@ -144,16 +147,16 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     const int igc = (EDGE && ig >= n) ? n - 1 : ig;
 #pragma unroll
     for (int k = 0; k < ERW; ++k) {
-      const int jr = c0 + w + 4 * k;
+      const int jr = c0 + w + ENW * k;
       const int jrc = (EDGE && jr >= n) ? n - 1 : jr;
       double v = row_ld(F + static_cast<long>(jrc) * ldf, igc);
       if (EDGE && !(jr < n && ig < n)) v = 0.0;
       bad |= !(v >= 0.0) || !(v <= 1.0e300);
-      sB[w + 4 * k][l] = v * rowc[4][w + 4 * k];
+      sB[w + ENW * k][l] = v * rowc[4][w + ENW * k];
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < ERW; ++k) sB[w + 4 * k][l] = a[k];
+    for (int k = 0; k < ERW; ++k) sB[w + ENW * k][l] = a[k];
   }
   __syncthreads();
 
@@ -163,7 +166,7 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
   const double cj = half ? 0.0 : aj * aj / nrays[jgc];
 #pragma unroll
   for (int k = 0; k < ERW; ++k) {
-    const int il = w + 4 * k;
+    const int il = w + ENW * k;
     const double ai = rowc[0][il];
     if (DIAG) {
       if (l == il) emax = fmax(emax, ai * a[k]);  // the diagonal keeps its value
@@ -180,35 +183,35 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     a[k] = eh * iai;
     sB[l][il] = bji;
     sb += bji;
-    // keep the 16 pair updates from being interleaved (register pressure)
+    // keep the pair updates from being interleaved (register pressure)
     __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
   if (DIAG) {
 #pragma unroll
     for (int k = 0; k < ERW; ++k)
-      if (l < w + 4 * k) a[k] = sB[w + 4 * k][l];  // written by the owner of the mirror
+      if (l < w + ENW * k) a[k] = sB[w + ENW * k][l];  // written by the owner of the mirror
   }
 
   // own tile back to F
 #pragma unroll
   for (int k = 0; k < ERW; ++k) {
-    const int i = r0 + w + 4 * k;
+    const int i = r0 + w + ENW * k;
     if (!EDGE || (i < n && jg < n)) row_st(F + static_cast<long>(i) * ldf, jg, a[k]);
   }
   if (!DIAG) {  // partner tile back to F
     const int ig = r0 + l;
 #pragma unroll
     for (int k = 0; k < ERW; ++k) {
-      const int jr = c0 + w + 4 * k;
-      if (!EDGE || (jr < n && ig < n)) row_st(F + static_cast<long>(jr) * ldf, ig, sB[w + 4 * k][l]);
+      const int jr = c0 + w + ENW * k;
+      if (!EDGE || (jr < n && ig < n)) row_st(F + static_cast<long>(jr) * ldf, ig, sB[w + ENW * k][l]);
     }
   }
   __syncthreads();
-  // own tile transposed into LDS, then each thread sums 16 entries of row l
+  // own tile transposed into LDS, then each thread sums ERW entries of row l
 #pragma unroll
-  for (int k = 0; k < ERW; ++k) sB[l][w + 4 * k] = a[k];
-  red[w][l] = sb;  // partner row l: this wave's 16 entries
+  for (int k = 0; k < ERW; ++k) sB[l][w + ENW * k] = a[k];
+  red[w][l] = sb;  // partner row l: this wave's ERW entries
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_xor(rmax, off));
     emax = fmax(emax, __shfl_xor(emax, off));
@@ -216,9 +219,9 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
   __syncthreads();
   double sa = 0.0;
 #pragma unroll
-  for (int k = 0; k < ERW; ++k) sa += sB[w + 4 * k][l];
+  for (int k = 0; k < ERW; ++k) sa += sB[w + ENW * k][l];
   __syncthreads();
-  red[ENF_THREADS / 64 + w][l] = sa;  // own row l: this wave's 16 entries
+  red[ENW + w][l] = sa;  // own row l: this wave's ERW entries
   if (l == 0) {
     sB[0][w] = rmax;
     sB[1][w] = emax;
@@ -227,8 +230,8 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
   if (w == 0) {
     double s_own = 0.0, s_par = 0.0;
 #pragma unroll
-    for (int q = 0; q < ENF_THREADS / 64; ++q) {
-      s_own += red[ENF_THREADS / 64 + q][l];
+    for (int q = 0; q < ENW; ++q) {
+      s_own += red[ENW + q][l];
       s_par += red[q][l];
     }
     const int t = in.t;
@@ -245,7 +248,7 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     }
     if (l == 0) {
       double x = sB[0][0], y = sB[1][0];
-      for (int q = 1; q < ENF_THREADS / 64; ++q) {
+      for (int q = 1; q < ENW; ++q) {
         x = fmax(x, sB[0][q]);
         y = fmax(y, sB[1][q]);
       }
@@ -259,7 +262,7 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
 __device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int first) {
   if (in.ctrl->converged || in.ctrl->status < 0) return;
   __shared__ double sB[ET][ETP];
-  __shared__ double red[2 * (ENF_THREADS / 64)][ET];  // per-wave row partials: partner, own
+  __shared__ double red[2 * (ENW)][ET];  // per-wave row partials: partner, own
   __shared__ double rowc[5][ET];                       // per-row constants
   int I, J;
   pair_from_index(pair, in.t, I, J);
@@ -275,7 +278,7 @@ __device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int
   }
 }
 
-__global__ void __launch_bounds__(ENF_THREADS, 2) enf_sweep(EnfInst in, int first) {
+__global__ void __launch_bounds__(ENF_THREADS, 4) enf_sweep(EnfInst in, int first) {
   enf_sweep_body(in, blockIdx.x, first);
 }
 
@@ -290,7 +293,7 @@ __device__ __forceinline__ int find_segment(const long* __restrict__ start, int 
 }
 
 // all instances of a batch in one grid: blocks [pair_start[k], pair_start[k+1]) are instance k
-__global__ void __launch_bounds__(ENF_THREADS, 2)
+__global__ void __launch_bounds__(ENF_THREADS, 4)
 enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair_start, int count, int first) {
   const int k = find_segment(pair_start, count, blockIdx.x);
   enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);
