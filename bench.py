@@ -96,8 +96,8 @@ def main() -> int:
                     help="headline: the 8192-face pipeline (default); batch64: 64 uneven models x 2 bands")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path - DESIGN.md describes how the solve would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path.", file=sys.stderr)
         return 2
 
     if args.workload == "batch64":
@@ -320,14 +320,16 @@ def run_batch64(args) -> int:
     pairs), two bands each (IR eps, solar alpha), 1e4 rays per face: one step
     restores every noisy F and runs the whole batch - enforcement of every
     instance (FRACVAR, each stops on the device at closure defect <= 1e-13),
-    then FP32 LU + solves and one FP64 refinement step for all 128 REF
-    matrices - replayed from one captured CUDA graph."""
+    then LU + solves of all 128 REF matrices - replayed from one captured CUDA
+    graph.  Two Gebhart variants are timed: FP64, and FP32 with one FP64
+    refinement step; the line reports the faster one whose error on the
+    three smallest instances is within 1e-10 of the oracle (or the one named
+    by --precision)."""
     import numpy as np
     import torch
 
     import oracle
     import paper_2511_04277_amd as rad
-    from paper_2511_04277_amd import _lib as L
     from synth import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm device"
@@ -343,61 +345,80 @@ def run_batch64(args) -> int:
     f0 = [d(i.f_noisy) for i in insts]
     models = [{"F": f.clone(), "area": d(i.area), "n_rays": d(i.n_rays), "eps": [d(e) for e in i.eps],
                "rho": [d(r) for r in i.rho]} for f, i in zip(f0, insts)]
-    batch = rad.Batch(models, precision="fp32_ir")
     iters = 80
-
-    def step():
-        for m, f in zip(models, f0):
-            m["F"].copy_(f)
-        batch.run(enforce_iters=iters, enforce_tol=1e-13, ir_steps=1)
-
-    step()
-    torch.cuda.synchronize()
-    st = batch.stats()
-    log(f"enforcement iterations per instance: min {min(x['iters'] for x in st)}, max {max(x['iters'] for x in st)}; "
-        f"all converged: {all(x['converged'] for x in st)}")
-    # accuracy on the smallest instances against the oracle (same enforced F)
+    variants = {"fp64": ("fp64", 0), "fp32_ir1": ("fp32_ir", 1)}
+    if args.precision in ("fp32_ir", "fp32_ir1"):
+        wanted = ["fp32_ir1"]
+    elif args.precision == "fp64":
+        wanted = ["fp64"]
+    else:
+        wanted = list(variants)
     order = np.argsort([i.n for i in insts])[:3]
-    errs = []
-    for k in order:
-        fk = models[k]["F"].cpu().numpy()
-        for b in range(2):
-            ref = oracle.gebhart_ref(fk, insts[k].eps[b], insts[k].rho[b])
-            errs.append(float(np.abs(batch.B[k][b].cpu().numpy() - ref).max()))
-    log(f"max|B - B_oracle| on the 3 smallest instances x 2 bands: {max(errs):.3e}")
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
+    ref_cache = {}
+    results = {}
+    for name in wanted:
+        prec, ir = variants[name]
+        batch = rad.Batch(models, precision=prec)
+
+        def step():
+            for m, f in zip(models, f0):
+                m["F"].copy_(f)
+            batch.run(enforce_iters=iters, enforce_tol=1e-13, ir_steps=ir)
+
         step()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        step()
-    for _ in range(args.warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    flops32 = sum(2 * (2.0 / 3.0 * i.n ** 3 + 2.0 * i.n * i.n * (i.n + 1)) + 2 * 2.0 * i.n * i.n * (i.n + 1)
-                  for i in insts)
-    flops64 = sum(2 * 2.0 * i.n * i.n * (i.n + 1) for i in insts)
+        torch.cuda.synchronize()
+        st = batch.stats()
+        log(f"[{name}] enforcement iterations per instance: min {min(x['iters'] for x in st)}, "
+            f"max {max(x['iters'] for x in st)}; all converged: {all(x['converged'] for x in st)}")
+        # accuracy on the smallest instances against the oracle (same enforced F)
+        errs = []
+        for k in order:
+            fk = models[k]["F"].cpu().numpy()
+            for b in range(2):
+                if (k, b) not in ref_cache:
+                    ref_cache[(k, b)] = oracle.gebhart_ref(fk, insts[k].eps[b], insts[k].rho[b])
+                errs.append(float(np.abs(batch.B[k][b].cpu().numpy() - ref_cache[(k, b)]).max()))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        results[name] = {"ms_per_step": ms, "ref_per_s": 128.0 * 1000.0 / ms, "ir_steps": ir,
+                         "max_abs_err_vs_oracle_smallest3": max(errs)}
+        log(f"[{name}] {ms:.2f} ms per step, {128e3 / ms:.1f} REF/s, max|B - B_oracle| on the 3 smallest "
+            f"instances x 2 bands: {max(errs):.3e}")
+        del g, batch
+        torch.cuda.synchronize()
+    ok = [k for k in wanted if results[k]["max_abs_err_vs_oracle_smallest3"] <= 1e-10]
+    choice = min(ok or wanted, key=lambda k: results[k]["ms_per_step"])
+    ms = results[choice]["ms_per_step"]
+    n3 = sum(float(i.n) ** 3 for i in insts)
     out = {
-        "metric": "REF matrices/sec, batch of 64 uneven-N models x 2 bands (FP32 LU + 1 FP64 refinement step)",
+        "metric": "REF matrices/sec, batch of 64 uneven-N models x 2 bands",
         "value": 128.0 * 1000.0 / ms, "unit": "REF matrices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if choice == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": "batch64: 64 models, N log-uniform [256, 4096], 2 bands, 1e4 rays/face",
                    "sum_n": int(sum(i.n for i in insts)), "enforce_iters_max": iters, "enforce_tol": 1e-13,
-                   "ir_steps": 1, "graph": True},
-        "algorithmic_tflops": {"fp32_lu_and_solves": flops32 / (ms * 1e-3) / 1e12,
-                               "fp64_residual": flops64 / (ms * 1e-3) / 1e12},
-        "max_abs_err_vs_oracle_smallest3": max(errs),
+                   "precision": choice, "ir_steps": variants[choice][1], "graph": True},
+        "variants": results,
+        # LU (2/3 N^3) + two bands of N x (N+1) solves (2 N^2 (N+1) each), per step
+        "solve_flops_per_step": sum(2.0 / 3.0 * i.n ** 3 + 2 * 2.0 * i.n * i.n * (i.n + 1) for i in insts),
+        "sum_n_cubed": n3,
     }
     print(json.dumps(out), flush=True)
     return 0
