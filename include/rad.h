@@ -288,7 +288,10 @@ int32_t rad_tuning_set(const rad_tuning* in);
  * algorithmic work of the launches (2 M N K flops and one pass over A, B and C
  * for a GEMM, C read too when accumulated; one read and one write
  * of the n x (n+1) matrix for an enforcement sweep; one read of it for an
- * aggregation).  Profiling adds two event records per launch.
+ * aggregation).  Profiling adds two event records per launch (several
+ * microseconds each on gfx950), so rad_profile_kinds restricts the timing to
+ * the kinds whose bit (1 << RAD_PROF_*) is set in mask (default: all); the
+ * other kinds then run without events.  Both settings are per host thread.
  */
 #define RAD_PROF_GEMM_F64 0      /* FP64 MFMA GEMM (factorization, solves, residual) */
 #define RAD_PROF_GEMM_F32 1      /* FP32 MFMA GEMM                                   */
@@ -307,6 +310,7 @@ typedef struct rad_kernel_profile {
 } rad_kernel_profile;
 
 int32_t rad_profile_enable(int32_t on);
+int32_t rad_profile_kinds(uint32_t mask);
 int32_t rad_profile_read(rad_kernel_profile* out, int32_t count);
 
 #ifdef __cplusplus

@@ -121,6 +121,7 @@ SIGNATURES = {
     "rad_tuning_get": (_I32, [ctypes.POINTER(RadTuning)]),
     "rad_tuning_set": (_I32, [ctypes.POINTER(RadTuning)]),
     "rad_profile_enable": (_I32, [_I32]),
+    "rad_profile_kinds": (_I32, [ctypes.c_uint32]),
     "rad_profile_read": (_I32, [ctypes.POINTER(RadKernelProfile), _I32]),
 }
 

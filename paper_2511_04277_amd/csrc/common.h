@@ -58,7 +58,7 @@ struct Carve {
 };
 
 // Per-launch kernel timing (see profile.hip).
-bool prof_enabled();
+bool prof_enabled(int kind);
 hipEvent_t prof_event();
 void prof_push(int kind, hipEvent_t a, hipEvent_t b, double flops, double bytes);
 
@@ -69,7 +69,7 @@ struct ProfScope {
   double flops, bytes;
   hipEvent_t a = nullptr;
   ProfScope(hipStream_t st, int k, double f, double b) : s(st), kind(k), flops(f), bytes(b) {
-    if (prof_enabled()) {
+    if (prof_enabled(k)) {
       a = prof_event();
       if (a) hipEventRecord(a, s);
     }

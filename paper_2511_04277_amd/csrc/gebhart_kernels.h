@@ -166,19 +166,21 @@ __global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) 
 
 // Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting, blocked by
 // 16.  The block is held as 8 x 8 tiles of 16 x 16 in MFMA accumulator layout:
-// wave w (of 16) owns tile row w/2, tile columns (w%2)*4 .. +3.  Step s takes
+// wave w (of 8) owns tile row w.  Step s takes
 // the 16 x 16 pivot tile P = M(s,s) and applies
 //   M(s,s) <- P^-1,   M(s,j) <- P^-1 M(s,j),   M(i,s) <- -M(i,s) P^-1,
 //   M(i,j) <- M(i,j) - M(i,s) P^-1 M(s,j)                 (i, j != s),
 // i.e. the scalar in-place Gauss-Jordan update with a 16 x 16 pivot; after
 // the 8 steps M = A^-1.  P is inverted inside one wave by 16 scalar
 // Gauss-Jordan steps with lane j holding column j (pivot row and column are
-// broadcast with lane reads, no barriers); the row products and the rank-16
-// updates run on the matrix cores.  Two workgroup barriers per step.
+// broadcast with lane reads, no barriers); the row products (one tile column
+// per wave) and the rank-16 updates run on the matrix cores, each wave
+// loading its tile-row operand once per step and each tile-column operand
+// once for all its tiles.  Two workgroup barriers per step.
 // Diagonal dominance of K makes every pivot order stable, so no pivoting is
 // needed; the scalar pivots are the same Schur-complement diagonals as in
 // unblocked elimination and are checked against the singularity threshold.
-constexpr int GJ_WAVES = 4;    // small enough to share a CU with one GEMM tile
+constexpr int GJ_WAVES = 8;    // one tile row per wave
 constexpr int GJ_THREADS = 64 * GJ_WAVES;
 
 // 1/x: hardware reciprocal refined by Newton steps to full precision
@@ -214,43 +216,46 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <class T, int NW>
 __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int BT = 16;              // pivot tile
-  constexpr int NT = NB / BT;         // 8 tiles per side
-  constexpr int TPW = NT * NT / NW;   // tiles per wave (linear tile id = w * TPW + b)
-  constexpr int LC = BT + 2;          // padded row of the column panel
-  constexpr int LR = NB + 2;          // padded row of the row panels
-  __shared__ T sC[2][NB][LC];         // old tile column s (double-buffered)
-  __shared__ T sRo[BT][LR];           // old tile row s
-  __shared__ T sR[BT][LR];            // new tile row s (R(s) = P^-1)
-  __shared__ T sP[BT][BT + 1];        // P^-1, row-major
+  constexpr int BT = 16;
+  constexpr int NT = NB / BT;
+  constexpr int RPW = NT / NW;        // tile rows per wave
+  static_assert(RPW * NW == NT, "NW must divide 8");
+  constexpr int LC = BT + 2;
+  constexpr int LR = NB + 2;
+  __shared__ T sC[2][NB][LC];
+  __shared__ T sRo[BT][LR];
+  __shared__ T sR[BT][LR];
+  __shared__ T sP[BT][BT + 1];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int li = l & 15, lg = l >> 4;
-  v4 m[TPW];
+  v4 m[RPW][NT];
 #pragma unroll
-  for (int b = 0; b < TPW; ++b) {
-    const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
+  for (int rr = 0; rr < RPW; ++rr)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      m[b][r] = A[static_cast<long>(bi * BT + Mfma<T>::orow(l, r)) * lda + bj * BT + li];
-  }
+    for (int bj = 0; bj < NT; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        m[rr][bj][r] = A[static_cast<long>((w * RPW + rr) * BT + Mfma<T>::orow(l, r)) * lda + bj * BT + li];
   const double tiny = sizeof(T) == 8 ? 1e-11 : 1e-5;
   int singular = 0;
 #pragma unroll 1
   for (int s = 0; s < NT; ++s) {
     const int cb = s & 1;
-    // publish the old tile column s and tile row s
+    const int sw = s / RPW, srr = s % RPW;  // owner wave of tile row s, its local row
 #pragma unroll
-    for (int b = 0; b < TPW; ++b) {
-      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
-      if (bj == s)
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int bi = w * RPW + rr;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sC[cb][bi * BT + Mfma<T>::orow(l, r)][li] = m[b][r];
-      if (bi == s)
+      for (int bj = 0; bj < NT; ++bj) {
+        if (bj == s)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sRo[Mfma<T>::orow(l, r)][bj * BT + li] = m[b][r];
+          for (int r = 0; r < 4; ++r) sC[cb][bi * BT + Mfma<T>::orow(l, r)][li] = m[rr][bj][r];
+        if (bi == s)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sRo[Mfma<T>::orow(l, r)][bj * BT + li] = m[rr][bj][r];
+      }
     }
-    // the owner of the pivot tile inverts it (lane j keeps column j)
-    if (w == (NT + 1) * s / TPW) {
+    if (w == sw) {
       wave_lds_sync();
       const int j = li;
       T c[BT];
@@ -282,45 +287,61 @@ __device__ __forceinline__ void gj_body(const T* __restrict__ A, long lda, T* __
       }
     }
     __syncthreads();
-    // new tile row s: R(s, j) = P^-1 Ro(s, j), R(s, s) = P^-1
+    // new tile row s, spread over the waves: R(s, j) = P^-1 Ro(s, j), R(s, s) = P^-1
+    {
+      T pa[4];
 #pragma unroll
-    for (int b = 0; b < TPW; ++b) {
-      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
-      if (bi != s) continue;
-      if (bj == s) {
+      for (int kk = 0; kk < 4; ++kk) pa[kk] = sP[li][4 * kk + lg];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) m[b][r] = sP[Mfma<T>::orow(l, r)][li];
-      } else {
-        v4 acc = v4{0, 0, 0, 0};
+      for (int jj = 0; jj < RPW; ++jj) {
+        const int bj = w * RPW + jj;
+        if (bj == s) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-          acc = Mfma<T>::mma(sP[li][4 * kk + lg], sRo[4 * kk + lg][bj * BT + li], acc);
-        m[b] = acc;
+          for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][bj * BT + li] = sP[Mfma<T>::orow(l, r)][li];
+        } else {
+          v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = Mfma<T>::mma(pa[kk], sRo[4 * kk + lg][bj * BT + li], acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][bj * BT + li] = acc[r];
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) sR[Mfma<T>::orow(l, r)][bj * BT + li] = m[b][r];
     }
     __syncthreads();
-    // rank-16 update of the other tile rows; tile column s becomes -M(i,s) P^-1
+    // rank-16 update of the other tile rows; tile column s becomes -M(i,s) P^-1;
+    // tile row s takes R(s, :)
+    T av[RPW][4];
 #pragma unroll
-    for (int b = 0; b < TPW; ++b) {
-      const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
-      if (bi == s) continue;
-      if (bj == s) m[b] = v4{0, 0, 0, 0};
+    for (int rr = 0; rr < RPW; ++rr)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        m[b] = Mfma<T>::mma(-sC[cb][bi * BT + li][4 * kk + lg], sR[4 * kk + lg][bj * BT + li], m[b]);
+      for (int kk = 0; kk < 4; ++kk) av[rr][kk] = -sC[cb][(w * RPW + rr) * BT + li][4 * kk + lg];
+#pragma unroll
+    for (int bj = 0; bj < NT; ++bj) {
+      T bv[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) bv[kk] = sR[4 * kk + lg][bj * BT + li];
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) {
+        if (w * RPW + rr == s) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m[rr][bj][r] = sR[Mfma<T>::orow(l, r)][bj * BT + li];
+          continue;
+        }
+        if (bj == s) m[rr][bj] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) m[rr][bj] = Mfma<T>::mma(av[rr][kk], bv[kk], m[rr][bj]);
+      }
     }
   }
 #pragma unroll
-  for (int b = 0; b < TPW; ++b) {
-    const int bi = (w * TPW + b) / NT, bj = (w * TPW + b) % NT;
+  for (int rr = 0; rr < RPW; ++rr)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[(bi * BT + Mfma<T>::orow(l, r)) * NB + bj * BT + li] = m[b][r];
-  }
+    for (int bj = 0; bj < NT; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[((w * RPW + rr) * BT + Mfma<T>::orow(l, r)) * NB + bj * BT + li] = m[rr][bj][r];
   if (singular) raise_status(&sc->status, RAD_ESINGULAR);
 }
-
 template <class T>
 __global__ void __launch_bounds__(GJ_THREADS)
 gj_inverse(const T* __restrict__ A, long lda, T* __restrict__ out, Scalars* sc) {

@@ -1,7 +1,8 @@
 // Optional per-launch timing of the hot kernels with HIP events.
 //
 // When enabled (rad_profile_enable, per host thread), every launch of a
-// profiled kernel is bracketed by two events on its stream; rad_profile_read
+// profiled kernel of a selected kind (rad_profile_kinds) is bracketed by two
+// events on its stream; rad_profile_read
 // waits for them and reports launches, summed device time and the launches'
 // algorithmic flops / bytes per kernel kind.
 #include <vector>
@@ -16,11 +17,12 @@ struct Rec {
   double flops, bytes;
 };
 thread_local bool g_on = false;
+thread_local uint32_t g_mask = 0xffffffffu;
 thread_local std::vector<Rec> g_recs;
 thread_local std::vector<hipEvent_t> g_pool;
 }  // namespace
 
-bool prof_enabled() { return g_on; }
+bool prof_enabled(int kind) { return g_on && kind >= 0 && kind < 32 && ((g_mask >> kind) & 1u); }
 
 hipEvent_t prof_event() {
   if (!g_pool.empty()) {
@@ -43,6 +45,11 @@ using namespace rad;
 
 extern "C" int32_t rad_profile_enable(int32_t on) {
   g_on = on != 0;
+  return RAD_OK;
+}
+
+extern "C" int32_t rad_profile_kinds(uint32_t mask) {
+  g_mask = mask;
   return RAD_OK;
 }
 
