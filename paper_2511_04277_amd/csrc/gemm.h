@@ -251,7 +251,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
 // XCD owns a contiguous range of logical tiles, then the logical tiles are
 // walked in groups of TILE_GROUP tile rows, column by column, so the tiles
 // one XCD runs at the same time share a few A row panels and B column panels
-// instead of touching a new B panel per tile.
+// instead of touching a new B panel per tile.  A block-triangular operand
+// makes the work per tile row differ (up to 8x), so those products walk whole
+// tile columns instead: each XCD then holds a range of columns with every
+// row, and all XCDs get the same work.
 constexpr int NUM_XCD = 8;
 constexpr int TILE_GROUP = 8;
 
@@ -261,10 +264,10 @@ __device__ __forceinline__ int xcd_contiguous(int pid, int total) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + loc;
 }
 
-__device__ __forceinline__ void grouped_tile(int L, int ntx, int nty, int& bx, int& by) {
-  const int per = TILE_GROUP * ntx;
-  const int grp = L / per, r0 = grp * TILE_GROUP;
-  const int gs = min(nty - r0, TILE_GROUP), w = L - grp * per;
+__device__ __forceinline__ void grouped_tile(int L, int ntx, int nty, int group, int& bx, int& by) {
+  const int per = group * ntx;
+  const int grp = L / per, r0 = grp * group;
+  const int gs = min(nty - r0, group), w = L - grp * per;
   by = r0 + w % gs;
   bx = w / gs;
 }
@@ -283,7 +286,7 @@ __global__ void __launch_bounds__(256, TS == GEMM_TILE ? 2 : 4) gemm_lds(GemmArg
   const int ntx = nt0 + nt1;
   const int nty = (g.M + TS - 1) / TS;
   int bx, by;
-  grouped_tile(xcd_contiguous(blockIdx.x, ntx * nty), ntx, nty, bx, by);
+  grouped_tile(xcd_contiguous(blockIdx.x, ntx * nty), ntx, nty, g.tri ? nty : TILE_GROUP, bx, by);
   gemm_tile<T, TRANS_A, TS>(g, bx, by);
 }
 
