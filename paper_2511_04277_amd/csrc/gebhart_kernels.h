@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) 
 
 // Gauss-Jordan inverse of one NB x NB diagonal block, no pivoting, blocked by
 // 16.  The block is held as 8 x 8 tiles of 16 x 16 in MFMA accumulator layout:
-// wave w (of 8) owns tile row w.  Step s takes
+// wave w (of 4) owns tile rows 2w and 2w+1.  Step s takes
 // the 16 x 16 pivot tile P = M(s,s) and applies
 //   M(s,s) <- P^-1,   M(s,j) <- P^-1 M(s,j),   M(i,s) <- -M(i,s) P^-1,
 //   M(i,j) <- M(i,j) - M(i,s) P^-1 M(s,j)                 (i, j != s),
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long count) 
 // Diagonal dominance of K makes every pivot order stable, so no pivoting is
 // needed; the scalar pivots are the same Schur-complement diagonals as in
 // unblocked elimination and are checked against the singularity threshold.
-constexpr int GJ_WAVES = 8;    // one tile row per wave
+constexpr int GJ_WAVES = 4;    // two tile rows per wave; at 254 VGPRs a wave fits on a SIMD beside one GEMM wave
 constexpr int GJ_THREADS = 64 * GJ_WAVES;
 
 // 1/x: hardware reciprocal refined by Newton steps to full precision
