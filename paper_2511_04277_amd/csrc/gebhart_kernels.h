@@ -453,10 +453,13 @@ __host__ __device__ inline bool tri_level_args(const TriJob<T>& j, int b, int st
   return true;
 }
 
-// Grid: panels x pairs x 2 matrices x (b/128)^2 tiles.
+// Grid: panels x pairs x 2 matrices x (b/64)^2 tiles of 64 x 64 (the joins
+// are short latency-bound products, so the smaller tile spreads them over
+// four times the CUs).
+constexpr int TRI_TS = 64;
 template <class T>
-__global__ void __launch_bounds__(256, 2) tri_level(TriJob<T> j, int b, int stage) {
-  const int tpg = (b / NB) * (b / NB);
+__global__ void __launch_bounds__(256, 4) tri_level(TriJob<T> j, int b, int stage) {
+  const int tpg = (b / TRI_TS) * (b / TRI_TS);
   const int nq = NB2 / (2 * b);
   int blk = blockIdx.x;
   const int tile = blk % tpg;
@@ -465,13 +468,13 @@ __global__ void __launch_bounds__(256, 2) tri_level(TriJob<T> j, int b, int stag
   blk /= 2;
   GemmArgs<T> g;
   if (!tri_level_args<T>(j, b, stage, blk / nq, blk % nq, mat, g)) return;
-  const int ntx = g.ntile[0], nty = (g.M + GEMM_TILE - 1) / GEMM_TILE;
+  const int ntx = (g.N[0] + TRI_TS - 1) / TRI_TS, nty = (g.M + TRI_TS - 1) / TRI_TS;
   if (tile >= ntx * nty) return;
-  gemm_tile<T, false>(g, tile % ntx, tile / ntx);
+  gemm_tile<T, false, TRI_TS>(g, tile % ntx, tile / ntx);
 }
 
 inline unsigned tri_level_blocks(int P2, int b) {
-  return static_cast<unsigned>(P2) * (NB2 / (2 * b)) * 2 * (b / NB) * (b / NB);
+  return static_cast<unsigned>(P2) * (NB2 / (2 * b)) * 2 * (b / TRI_TS) * (b / TRI_TS);
 }
 
 // dst rows [0, rows) <- src, columns < cols (same precision)
