@@ -256,14 +256,17 @@ void rad_batch_plan_destroy(rad_batch_plan* plan);
 
 /* ---- tuning ------------------------------------------------------------ */
 /*
- * Process-wide knobs of the kernels (defaults: 0, 0, 1), normally applied by
- * the binding from the autotuner's table (paper_2511_04277_amd/tuning.json):
+ * Process-wide knobs of the kernels (defaults: 0, 0, 1, 0), normally applied
+ * by the binding from the autotuner's table (paper_2511_04277_amd/tuning.json):
  *   small_tile_below_f64 / _f32: a GEMM with fewer 128 x 128 output tiles
  *     than this runs with 64 x 64 tiles (more workgroups for narrow or short
  *     products); 0 keeps 128 x 128 everywhere;
  *   lookahead: 1 updates the next panel's columns on the caller's stream and
  *     the rest of the trailing matrix on a second stream during the
- *     factorization; 0 keeps every update on the caller's stream.
+ *     factorization; 0 keeps every update on the caller's stream;
+ *   side_chunk_tiles: with look-ahead, the second stream's update is issued
+ *     as row chunks of at most this many 128 x 128 tiles, so launches of the
+ *     caller's stream get dispatched between them; 0 issues one launch.
  * Results do not depend on the knobs beyond rounding of the same operations
  * in the same order per element (they are bitwise identical).  Not
  * synchronised: set them while no call is running.
@@ -272,7 +275,7 @@ typedef struct rad_tuning {
   int32_t small_tile_below_f64;
   int32_t small_tile_below_f32;
   int32_t lookahead;
-  int32_t reserved;
+  int32_t side_chunk_tiles;
 } rad_tuning;
 
 int32_t rad_tuning_get(rad_tuning* out);

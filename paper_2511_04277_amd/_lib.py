@@ -74,7 +74,7 @@ class RadTuning(ctypes.Structure):
         ("small_tile_below_f64", ctypes.c_int32),
         ("small_tile_below_f32", ctypes.c_int32),
         ("lookahead", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("side_chunk_tiles", ctypes.c_int32),
     ]
 
 
@@ -131,16 +131,17 @@ TUNING_PATH = _PKG / "tuning.json"
 
 def apply_tuning(chosen: dict) -> None:
     """Set the library's runtime knobs (rad_tuning_set) from a dict with keys
-    small_tile_below_f64, small_tile_below_f32, lookahead."""
+    small_tile_below_f64, small_tile_below_f32, lookahead and optionally
+    side_chunk_tiles (0 when absent)."""
     t = RadTuning(int(chosen["small_tile_below_f64"]), int(chosen["small_tile_below_f32"]),
-                  int(chosen["lookahead"]), 0)
+                  int(chosen["lookahead"]), int(chosen.get("side_chunk_tiles", 0)))
     check(lib().rad_tuning_set(ctypes.byref(t)), "rad_tuning_set")
 
 
 def tuning() -> dict:
     t = RadTuning()
     check(lib().rad_tuning_get(ctypes.byref(t)), "rad_tuning_get")
-    return {name: getattr(t, name) for name, _ in t._fields_ if name != "reserved"}
+    return {name: getattr(t, name) for name, _ in t._fields_}
 
 
 def lib() -> ctypes.CDLL:

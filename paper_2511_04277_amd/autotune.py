@@ -9,6 +9,9 @@ candidate of
   * small_tile_below: GEMMs with fewer 128 x 128 output tiles than this run
     with 64 x 64 tiles (0 = never, a huge value = always);
   * lookahead: split each trailing update over two streams (0 / 1);
+  * side_chunk_tiles: with look-ahead, the second stream's update in row
+    chunks of at most this many 128 x 128 tiles (0 = one launch), tried
+    with the best of the two knobs above;
 
 keeps the fastest (summed over the sizes) and writes the table to
 ``paper_2511_04277_amd/tuning.json``, which the binding applies when the
@@ -28,6 +31,7 @@ import time
 
 TUNING_PATH = pathlib.Path(__file__).resolve().parent / "tuning.json"
 TILE_CANDIDATES = [0, 256, 1024, 4096, 1 << 30]
+CHUNK_CANDIDATES = [256, 384, 512, 768, 1024, 2048]
 
 
 def _system(n: int, seed: int, device):
@@ -75,8 +79,9 @@ def tune(sizes, reps: int, out_path: pathlib.Path = TUNING_PATH, log=print) -> d
     for precision in ("fp64", "fp32_ir"):
         ref = {}
         results = []
-        for tile, look in itertools.product(TILE_CANDIDATES, (1, 0)):
-            tun = L.RadTuning(tile, tile, look, 0)
+
+        def measure(tile, look, chunk):
+            tun = L.RadTuning(tile, tile, look, chunk)
             L.check(lib.rad_tuning_set(ctypes.byref(tun)), "rad_tuning_set")
             total = 0.0
             per = {}
@@ -85,21 +90,31 @@ def tune(sizes, reps: int, out_path: pathlib.Path = TUNING_PATH, log=print) -> d
                 if n not in ref:
                     ref[n] = B.clone()
                 elif not torch.equal(B, ref[n]):
-                    raise RuntimeError(f"tuning changed the result (n={n}, tile={tile}, lookahead={look})")
+                    raise RuntimeError(f"tuning changed the result (n={n}, tile={tile}, lookahead={look}, "
+                                       f"side_chunk_tiles={chunk})")
                 per[n] = ms
                 total += ms
-            results.append((total, tile, look, per))
+            results.append((total, tile, look, chunk, per))
             table.append({"precision": precision, "small_tile_below": tile, "lookahead": look,
-                          "ms": {str(k): round(v, 3) for k, v in per.items()}})
-            log(f"[autotune] {precision} small_tile_below={tile} lookahead={look}: "
+                          "side_chunk_tiles": chunk, "ms": {str(k): round(v, 3) for k, v in per.items()}})
+            log(f"[autotune] {precision} small_tile_below={tile} lookahead={look} side_chunk_tiles={chunk}: "
                 + ", ".join(f"n={k} {v:.2f} ms" for k, v in per.items()))
-        total, tile, look, _ = min(results, key=lambda r: r[0])
-        best[precision] = {"small_tile_below": tile, "lookahead": look, "total_ms": round(total, 3)}
-        log(f"[autotune] {precision}: best small_tile_below={tile} lookahead={look} ({total:.2f} ms)")
+
+        for tile, look in itertools.product(TILE_CANDIDATES, (1, 0)):
+            measure(tile, look, 0)
+        _, tile, look, _, _ = min(results, key=lambda r: r[0])
+        if look:
+            for chunk in CHUNK_CANDIDATES:
+                measure(tile, 1, chunk)
+        total, tile, look, chunk, _ = min(results, key=lambda r: r[0])
+        best[precision] = {"small_tile_below": tile, "lookahead": look, "side_chunk_tiles": chunk,
+                           "total_ms": round(total, 3)}
+        log(f"[autotune] {precision}: best small_tile_below={tile} lookahead={look} side_chunk_tiles={chunk} "
+            f"({total:.2f} ms)")
     # one look-ahead setting serves both precisions: the FP64 choice
     chosen = {"small_tile_below_f64": best["fp64"]["small_tile_below"],
               "small_tile_below_f32": best["fp32_ir"]["small_tile_below"],
-              "lookahead": best["fp64"]["lookahead"]}
+              "lookahead": best["fp64"]["lookahead"], "side_chunk_tiles": best["fp64"]["side_chunk_tiles"]}
     doc = {"device": torch.cuda.get_device_name(0), "sizes": list(sizes), "reps": reps,
            "chosen": chosen, "best": best, "measurements": table}
     out_path.write_text(json.dumps(doc, indent=1) + "\n")

@@ -126,8 +126,22 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
                             ldk, f.np - c2);
       if (Y) gemm_add_segment<T>(v, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
       if (v.nseg) {
-        hipError_t ge = launch_gemm(v, false, s2);
-        if (ge != hipSuccess) return ge;
+        // optionally in row chunks: a launch of s is dispatched only after
+        // the grid ahead of it on the other stream has been dispatched whole
+        int rows = f.np - c1;
+        const int chunk_tiles = gemm_tuning().side_chunk_tiles;
+        if (chunk_tiles > 0 && s2 != s) {
+          const int tx = gemm_tiles<T>(v) / ((v.M + GEMM_TILE - 1) / GEMM_TILE);  // column tiles
+          rows = std::max(1, chunk_tiles / std::max(1, tx)) * GEMM_TILE;
+        }
+        for (int r0 = 0; r0 < v.M; r0 += rows) {
+          GemmArgs<T> vc = v;
+          vc.A = v.A + static_cast<long>(r0) * ldk;
+          vc.M = std::min(rows, v.M - r0);
+          for (int q = 0; q < vc.nseg; ++q) vc.C[q] = v.C[q] + static_cast<long>(r0) * v.ldc[q];
+          hipError_t ge = launch_gemm(vc, false, s2);
+          if (ge != hipSuccess) return ge;
+        }
       }
     }
   }

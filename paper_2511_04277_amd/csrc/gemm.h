@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(256, TS == GEMM_TILE ? 2 : 4) gemm_lds(GemmArg
 // tiles.  Set by rad_tuning_set (tuning.cpp), chosen by the autotuner.
 struct GemmTuning {
   int small_tile_below[2];
+  int side_chunk_tiles;  // row chunks of the side-stream trailing update (0: one launch)
 };
 GemmTuning& gemm_tuning();
 

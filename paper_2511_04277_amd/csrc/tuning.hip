@@ -5,7 +5,7 @@
 
 namespace rad {
 namespace {
-GemmTuning g_gemm{{0, 0}};
+GemmTuning g_gemm{{0, 0}, 0};
 int g_lookahead = 1;
 }
 GemmTuning& gemm_tuning() { return g_gemm; }
@@ -22,18 +22,20 @@ extern "C" int32_t rad_tuning_get(rad_tuning* out) {
   out->small_tile_below_f64 = rad::g_gemm.small_tile_below[0];
   out->small_tile_below_f32 = rad::g_gemm.small_tile_below[1];
   out->lookahead = rad::g_lookahead;
+  out->side_chunk_tiles = rad::g_gemm.side_chunk_tiles;
   return RAD_OK;
 }
 
 extern "C" int32_t rad_tuning_set(const rad_tuning* in) {
   rad::clear_error();
   if (!in || in->small_tile_below_f64 < 0 || in->small_tile_below_f32 < 0 || in->lookahead < 0 ||
-      in->lookahead > 1) {
+      in->lookahead > 1 || in->side_chunk_tiles < 0) {
     rad::set_error("rad_tuning_set: NULL or out-of-range field");
     return RAD_EINVAL;
   }
   rad::g_gemm.small_tile_below[0] = in->small_tile_below_f64;
   rad::g_gemm.small_tile_below[1] = in->small_tile_below_f32;
   rad::g_lookahead = in->lookahead;
+  rad::g_gemm.side_chunk_tiles = in->side_chunk_tiles;
   return RAD_OK;
 }

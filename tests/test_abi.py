@@ -48,11 +48,15 @@ def test_tuning_roundtrip_and_validation():
     lib = _lib.lib()
     saved = _lib.tuning()
     try:
-        _lib.apply_tuning({"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0})
-        assert _lib.tuning() == {"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0}
+        _lib.apply_tuning({"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0,
+                           "side_chunk_tiles": 512})
+        assert _lib.tuning() == {"small_tile_below_f64": 300, "small_tile_below_f32": 7, "lookahead": 0,
+                                 "side_chunk_tiles": 512}
         bad = _lib.RadTuning(-1, 0, 1, 0)
         assert lib.rad_tuning_set(_lib.ctypes.byref(bad)) == _lib.RAD_EINVAL
         bad = _lib.RadTuning(0, 0, 2, 0)
+        assert lib.rad_tuning_set(_lib.ctypes.byref(bad)) == _lib.RAD_EINVAL
+        bad = _lib.RadTuning(0, 0, 1, -3)
         assert lib.rad_tuning_set(_lib.ctypes.byref(bad)) == _lib.RAD_EINVAL
         assert _lib.tuning()["small_tile_below_f64"] == 300  # unchanged by a rejected call
     finally:

@@ -167,8 +167,9 @@ def test_full_size_open_box_n16384_sampled_columns():
 
 
 def test_tuning_knobs_leave_results_bitwise_unchanged():
-    """Tile shape and look-ahead reorder launches only: B and the adjoint's
-    gradients must be identical under every setting."""
+    """Tile shape, look-ahead and the side update's chunking reorder launches
+    only: B and the adjoint's gradients must be identical under every
+    setting."""
     need_gpu()
     import paper_2511_04277_amd as rad
     from paper_2511_04277_amd import _lib as L
@@ -178,8 +179,9 @@ def test_tuning_knobs_leave_results_bitwise_unchanged():
     saved = L.tuning()
     outs = []
     try:
-        for tile, look in ((0, 1), (4096, 1), (1 << 30, 0), (256, 0)):
-            L.apply_tuning({"small_tile_below_f64": tile, "small_tile_below_f32": tile, "lookahead": look})
+        for tile, look, chunk in ((0, 1, 0), (4096, 1, 0), (1 << 30, 0, 0), (256, 0, 0), (4096, 1, 512), (0, 1, 100)):
+            L.apply_tuning({"small_tile_below_f64": tile, "small_tile_below_f32": tile, "lookahead": look,
+                            "side_chunk_tiles": chunk})
             for prec in ("fp64", "fp32_ir"):
                 b, fac, _ = rad.gebhart_ref(fd, eps, rho, precision=prec, ir_tol=1e-13, ir_max=3)
                 ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, fd, rho, b, g)
