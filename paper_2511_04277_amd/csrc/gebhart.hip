@@ -182,71 +182,121 @@ hipError_t panel_inverses(const Fact<T>& f, T* tmp, long ldt, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Y_p <- op(M_p) Y_p for panel p with a triangular panel inverse M_p, through
-// the scratch S (one panel of right-hand sides)
+// Panel products of the back and transposed solves.  Y_p <- op(M_p) Y_p goes
+// through one of two scratch panels S[0], S[1] (alternating); the update of
+// the other rows reads the product straight from the scratch, and the copy
+// back into Y_p runs on the side stream, off the chain of products and
+// updates.  Before a scratch panel is overwritten, s waits for the side
+// stream's latest copy (issued a whole update earlier, so long finished).
 template <class T>
-hipError_t apply_panel_inverse(const T* Mp, long ldm, bool trans, int tri, int c0, int L, T* Y, long ldy, int wy,
-                               T* S, long lds, hipStream_t s) {
-  GemmArgs<T> a = gemm_args<T>(Mp, ldm, L, L, T(1), T(0));
-  a.tri = tri;
-  gemm_add_segment<T>(a, Y + static_cast<long>(c0) * ldy, ldy, S, lds, wy);
-  RAD_GEMM(a, trans);
-  hipLaunchKernelGGL(copy_rows<T>, dim3(L), dim3(256), 0, s, S, lds, Y + static_cast<long>(c0) * ldy, ldy, wy);
-  return hipGetLastError();
-}
+struct PanelSweep {
+  T* S[2];
+  long lds;
+  hipStream_t s, s2;
+  SideStream* ss;
+  int idx = 0;
+  T* cur = nullptr;
+
+  hipError_t init(T* scr, long ld, hipStream_t st) {
+    S[0] = scr;
+    S[1] = scr + static_cast<long>(NB2) * ld;
+    lds = ld;
+    s = st;
+    hipError_t e = side_stream(&ss);
+    if (e != hipSuccess) return e;
+    s2 = lookahead_enabled() ? ss->s2 : s;
+    return hipSuccess;
+  }
+  // product of panel rows c0..c0+L into the next scratch panel; returns it in cur
+  hipError_t product(const T* Mp, long ldm, bool trans, int tri, int c0, int L, const T* Y, long ldy, int wy) {
+    if (idx >= 2) {
+      hipError_t e = hipStreamWaitEvent(s, ss->ev[1], 0);
+      if (e != hipSuccess) return e;
+    }
+    cur = S[idx & 1];
+    ++idx;
+    GemmArgs<T> a = gemm_args<T>(Mp, ldm, L, L, T(1), T(0));
+    a.tri = tri;
+    gemm_add_segment<T>(a, Y + static_cast<long>(c0) * ldy, ldy, cur, lds, wy);
+    return launch_gemm(a, trans, s);
+  }
+  // copy of the current product into Y_p, on the side stream
+  hipError_t copy_back(int c0, int L, T* Y, long ldy, int wy) {
+    hipError_t e = stream_wait(s2, s, ss->ev[0]);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_rows<T>, dim3(L), dim3(256), 0, s2, cur, lds, Y + static_cast<long>(c0) * ldy, ldy, wy);
+    return hipEventRecord(ss->ev[1], s2);
+  }
+  hipError_t join() { return stream_wait(s, s2, ss->ev[2]); }
+};
 
 // Y <- U^{-1} Y in place (all np rows; padded rows stay zero): per panel from
 // the last, Y_p <- W_p Y_p, then the rows above take the panel's contribution
 // in one K = panel-width product.
 template <class T>
-hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* S, long lds, hipStream_t s) {
+hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s) {
   const long ldk = f.ldk;
+  PanelSweep<T> ps;
+  hipError_t e = ps.init(scr, lds, s);
+  if (e != hipSuccess) return e;
   const int last_c0 = ((f.np - 1) / NB2) * NB2;
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
-    hipError_t e = apply_panel_inverse<T>(Wp, f.ldw, false, 1, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    e = ps.product(Wp, f.ldw, false, 1, c0, c1 - c0, Y, ldy, wy);
+    if (e != hipSuccess) return e;
+    e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c0 > 0) {
       GemmArgs<T> u = update_args<T>(f.kf + c0, ldk, c0, c1 - c0);
-      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
+      gemm_add_segment<T>(u, ps.cur, lds, Y, ldy, wy);
       RAD_GEMM(u, false);
     }
   }
-  return hipSuccess;
+  return ps.join();
 }
 
 // Y <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z, panel by panel
 // with the transposed panel inverses.
 template <class T>
-hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* S, long lds, hipStream_t s) {
+hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s) {
   const long ldk = f.ldk;
+  PanelSweep<T> ps;
+  hipError_t e = ps.init(scr, lds, s);
+  if (e != hipSuccess) return e;
   // U^T Z = Y: forward over panels (op(W_p) = W_p^T is lower triangular)
   for (int c0 = 0; c0 < f.np; c0 += NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
-    hipError_t e = apply_panel_inverse<T>(Wp, f.ldw, true, 2, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    e = ps.product(Wp, f.ldw, true, 2, c0, c1 - c0, Y, ldy, wy);
+    if (e != hipSuccess) return e;
+    e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + c1, ldk, f.np - c1, c1 - c0);
-      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y + static_cast<long>(c1) * ldy, ldy, wy);
+      gemm_add_segment<T>(u, ps.cur, lds, Y + static_cast<long>(c1) * ldy, ldy, wy);
       RAD_GEMM(u, true);
     }
   }
+  // the second pass reads every panel of Z, so the copies must have landed
+  e = ps.join();
+  if (e != hipSuccess) return e;
   // L^T Lambda = Z: backward over panels (op(V_p) = V_p^T is upper triangular)
   const int last_c0 = ((f.np - 1) / NB2) * NB2;
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Vp = f.V + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
-    hipError_t e = apply_panel_inverse<T>(Vp, f.ldw, true, 1, c0, c1 - c0, Y, ldy, wy, S, lds, s);
+    e = ps.product(Vp, f.ldw, true, 1, c0, c1 - c0, Y, ldy, wy);
+    if (e != hipSuccess) return e;
+    e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk, ldk, c0, c1 - c0);
-      gemm_add_segment<T>(u, Y + static_cast<long>(c0) * ldy, ldy, Y, ldy, wy);
+      gemm_add_segment<T>(u, ps.cur, lds, Y, ldy, wy);
       RAD_GEMM(u, true);
     }
   }
-  return hipSuccess;
+  return ps.join();
 }
 
 struct GebWork {
@@ -259,7 +309,7 @@ struct GebWork {
   double* p;    // FP64 P = F_sq diag(rho) (np x ldp), refinement only
   long ldp;
   double* part; // grad_eps partial sums (adjoint)
-  void* scr;    // (T) one panel of right-hand sides (NB2 x ldy), shared with
+  void* scr;    // (T) two panels of right-hand sides (2 NB2 x ldy), shared with
                 // the panel-inverse products (tri_tmp_elems, ld ldt)
   long ldt;
   size_t bytes;
@@ -289,7 +339,8 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
     const long pad = static_cast<long>(128 / es);
     const int P2 = static_cast<int>(ceil_div(np, NB2));
     w.ldt = tri_ldt(pad);
-    const size_t elems = std::max(static_cast<size_t>(NB2) * w.ldy, tri_tmp_elems(P2, pad));
+    // two panels of right-hand sides for the back and transposed solves
+    const size_t elems = std::max(static_cast<size_t>(2 * NB2) * w.ldy, tri_tmp_elems(P2, pad));
     w.scr = cv.take<char>(elems * es);
   }
   w.bytes = cv.used;
