@@ -93,8 +93,9 @@ __device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[NBR
 // once, with 16-byte global loads, into double-buffered LDS; the four waves
 // (2 x 2, each TS/2 x TS/2) read their MFMA fragments from LDS.  Within a K
 // chunk, lane group g takes k = g KC/4 + s at MFMA step s.  One barrier per
-// chunk.  TS = 128 for large products; TS = 64 gives four times the
-// workgroups for narrow or short ones.
+// chunk; global loads run two chunks ahead of the MFMAs.  TS = 128 for
+// large products; TS = 64 gives four times the workgroups for narrow or
+// short ones.
 //
 // Operand contract (all operands are the solver's own padded buffers):
 // op(A) is readable for rows < roundup(M, 128) and k < roundup(K, 32), B for
@@ -210,7 +211,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
 #pragma unroll
     for (int b = 0; b < NBR; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  T ra[E], rb[E];
+  // two register stages: chunk c + 2 is loaded from global memory while
+  // chunk c is multiplied from LDS and chunk c + 1 (loaded one chunk
+  // earlier) is stored to the other LDS buffer, so each load has a whole
+  // chunk of MFMAs to arrive
+  T ra0[E], rb0[E], ra1[E], rb1[E];
   // K range of this row tile: a triangular op(A) is zero by 128-blocks, so
   // the row tile skips the blocks left (upper) or right (lower) of its block
   const int mb = (m0 / GEMM_TILE) * GEMM_TILE;
@@ -218,14 +223,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
   const int kend = g.tri == 2 ? min(K, mb + GEMM_TILE) : K;
   const int nch = kend > kbeg ? (kend - kbeg + KC - 1) / KC : 0;
   if (nch > 0) {
-    lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg, ra, rb);
-    lds_stage_store<T, TRANS_A, TS>(sA[0], sB[0], ra, rb);
+    lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg, ra0, rb0);
+    lds_stage_store<T, TRANS_A, TS>(sA[0], sB[0], ra0, rb0);
   }
+  if (nch > 1) lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg + KC, ra1, rb1);
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    const bool more = c + 1 < nch;
-    if (more) lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg + (c + 1) * KC, ra, rb);
+  // chunk c from LDS buffer buf; la/lb receive chunk c + 2, sa/sb hold c + 1
+  auto step = [&](int c, int buf, T (&la)[E], T (&lb)[E], const T (&sa)[E], const T (&sb)[E]) {
+    if (c + 2 < nch) lds_stage_load<T, TRANS_A, TS>(A, lda, Bm, ldb, m0, n0, kbeg + (c + 2) * KC, la, lb);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = lg * (KC / 4) + s;
@@ -240,8 +245,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
 #pragma unroll
         for (int y = 0; y < NBR; ++y) acc[x][y] = Mfma<T>::mma(fa[x], fb[y], acc[x][y]);
     }
-    if (more) lds_stage_store<T, TRANS_A, TS>(sA[buf ^ 1], sB[buf ^ 1], ra, rb);
+    if (c + 1 < nch) lds_stage_store<T, TRANS_A, TS>(sA[buf ^ 1], sB[buf ^ 1], sa, sb);
     __syncthreads();
+  };
+  for (int c = 0; c < nch; c += 2) {
+    step(c, 0, ra0, rb0, ra1, rb1);
+    if (c + 1 < nch) step(c + 1, 1, ra1, rb1, ra0, rb0);
   }
   store_tile<T, NBR>(acc, g, Cm, ldc, M, N, m0 + wr, n0 + wc, l);
 }
