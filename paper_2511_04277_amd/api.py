@@ -45,13 +45,15 @@ def _vec(t: Optional[torch.Tensor], name: str, n: int, dtype=torch.float64):
 
 
 class _Workspace:
-    """Per-device scratch buffers, grown on demand and reused across calls."""
+    """Per-device, per-stream scratch buffers, grown on demand and reused
+    across calls (calls on different streams may run concurrently, so they
+    never share one)."""
 
     def __init__(self):
         self._bufs = {}
 
     def get(self, device: torch.device, key: str, nbytes: int) -> torch.Tensor:
-        k = (device.index, key)
+        k = (device.index, torch.cuda.current_stream(device).cuda_stream, key)
         buf = self._bufs.get(k)
         if buf is None or buf.numel() < nbytes:
             buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
