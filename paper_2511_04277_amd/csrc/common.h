@@ -103,6 +103,22 @@ inline hipError_t stream_wait(hipStream_t dst, hipStream_t src, hipEvent_t ev) {
 // smallest (most negative) code wins via atomicMin).
 __device__ inline void raise_status(int* flag, int code) { atomicMin(flag, code); }
 
+// tile pair (I, J), I <= J, of index p in the row-wise enumeration of the
+// upper triangle of a t x t tile grid
+__device__ inline void pair_from_index(long p, int t, int& I, int& J) {
+  // row-wise enumeration of the upper triangle (I <= J) of a t x t tile grid
+  double tt = 2.0 * t + 1.0;
+  int i = static_cast<int>((tt - sqrt(tt * tt - 8.0 * static_cast<double>(p))) * 0.5);
+  if (i < 0) i = 0;
+  if (i > t - 1) i = t - 1;
+  auto start = [t](long r) { return r * t - r * (r - 1) / 2; };
+  while (i > 0 && start(i) > p) --i;
+  while (i + 1 < t && start(i + 1) <= p) ++i;
+  I = i;
+  J = static_cast<int>(i + (p - start(i)));
+}
+
+
 // Non-negative doubles order like their bit patterns: atomicMax on the
 // bits gives an order-independent, reproducible max.
 __device__ inline void atomic_max_nonneg(double* p, double v) {

@@ -22,18 +22,6 @@ struct EnfCtrl {
   double last_defect, last_recip;
 };
 
-__device__ inline void pair_from_index(long p, int t, int& I, int& J) {
-  // row-wise enumeration of the upper triangle (I <= J) of a t x t tile grid
-  double tt = 2.0 * t + 1.0;
-  int i = static_cast<int>((tt - sqrt(tt * tt - 8.0 * static_cast<double>(p))) * 0.5);
-  if (i < 0) i = 0;
-  if (i > t - 1) i = t - 1;
-  auto start = [t](long r) { return r * t - r * (r - 1) / 2; };
-  while (i > 0 && start(i) > p) --i;
-  while (i + 1 < t && start(i + 1) <= p) ++i;
-  I = i;
-  J = static_cast<int>(i + (p - start(i)));
-}
 
 // One enforcement problem as the kernels see it.
 struct EnfInst {

@@ -469,9 +469,18 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
   return RAD_OK;
 }
 
+namespace {
+// REF check workspace: closure maxima per 4-row block, reciprocity maxima per tile pair
+size_t ref_check_bytes(int64_t n) {
+  const int64_t t = ceil_div(n, 64);
+  return align_up(static_cast<size_t>(ceil_div(n, 4)) * sizeof(double), 256) +
+         align_up(static_cast<size_t>(t * (t + 1) / 2) * sizeof(double), 256);
+}
+}  // namespace
+
 extern "C" size_t rad_ref_check_workspace_bytes(int64_t n) {
   if (n < 1) return 0;
-  return align_up(sizeof(Scalars), 256);
+  return ref_check_bytes(n);
 }
 
 extern "C" int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const double* eps,
@@ -480,18 +489,20 @@ extern "C" int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const 
   clear_error();
   RAD_REQUIRE(n >= 1 && ldb >= n + 1, RAD_EINVAL, "rad_ref_check: bad n or ldb");
   RAD_REQUIRE(B && eps && area && out, RAD_EINVAL, "rad_ref_check: NULL pointer");
-  RAD_REQUIRE(work && wbytes >= sizeof(Scalars) && reinterpret_cast<uintptr_t>(work) % 256 == 0,
+  RAD_REQUIRE(n <= (1 << 20), RAD_EINVAL, "rad_ref_check: n out of range");
+  RAD_REQUIRE(work && wbytes >= ref_check_bytes(n) && reinterpret_cast<uintptr_t>(work) % 256 == 0,
               RAD_EWORKSPACE, "rad_ref_check: workspace too small or misaligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Scalars* sc = static_cast<Scalars*>(work);
   const int ni = static_cast<int>(n);
-  hipLaunchKernelGGL(scalars_init, dim3(1), dim3(64), 0, s, sc);
-  hipLaunchKernelGGL(ref_closure, dim3(static_cast<unsigned>(ceil_div(n, 4))), dim3(256), 0, s, B,
-                     static_cast<long>(ldb), ni, sc);
-  const unsigned t = static_cast<unsigned>(ceil_div(n, 64));
-  hipLaunchKernelGGL(ref_reciprocity, dim3(t, t), dim3(256), 0, s, B, static_cast<long>(ldb), ni, eps,
-                     area, sc);
-  hipLaunchKernelGGL(copy_scalars_out, dim3(1), dim3(64), 0, s, sc, out);
+  const int t = static_cast<int>(ceil_div(n, 64));
+  const long pairs = static_cast<long>(t) * (t + 1) / 2;
+  const int nc = static_cast<int>(ceil_div(n, 4));
+  double* bc = static_cast<double*>(work);
+  double* br = reinterpret_cast<double*>(static_cast<char*>(work) + align_up(static_cast<size_t>(nc) * sizeof(double), 256));
+  hipLaunchKernelGGL(ref_closure, dim3(static_cast<unsigned>(nc)), dim3(256), 0, s, B, static_cast<long>(ldb), ni, bc);
+  hipLaunchKernelGGL(ref_reciprocity, dim3(static_cast<unsigned>(pairs)), dim3(256), 0, s, B, static_cast<long>(ldb),
+                     ni, t, eps, area, br);
+  hipLaunchKernelGGL(ref_final, dim3(1), dim3(256), 0, s, bc, nc, br, pairs, out);
   RAD_HIP_CHECK(hipGetLastError());
   return RAD_OK;
 }

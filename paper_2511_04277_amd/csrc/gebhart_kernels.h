@@ -558,49 +558,92 @@ load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long 
     y[j] = (j <= n && i < n) ? static_cast<T>(G[static_cast<long>(i) * ldg + j]) : T(0);
 }
 
-// REF closure residual: one wave per row, fixed-order reduction.
+
+// REF closure residual: one wave per row sums the n+1 entries; the block's
+// maximum of |s_i - 1| goes to blk[blockIdx.x] (no same-address atomics).
 __global__ void __launch_bounds__(256)
-ref_closure(const double* __restrict__ B, long ldb, int n, Scalars* sc) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
+ref_closure(const double* __restrict__ B, long ldb, int n, double* __restrict__ blk) {
+  __shared__ double red[4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + w;
   double s = 0.0;
-  if (row < n)
-    for (int j = l; j <= n; j += 64) s += B[static_cast<long>(row) * ldb + j];
+  if (row < n) {
+    const double* __restrict__ b = B + static_cast<long>(row) * ldb;
+    for (int j = l; j <= n; j += 64) s += b[j];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  double d = (row < n) ? fabs(s - 1.0) : 0.0;
-  if (l == 0) atomic_max_nonneg(&sc->red[0], d);
+  if (l == 0) red[w] = (row < n) ? fabs(s - 1.0) : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) blk[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-// REF reciprocity residual max |eps_i A_i B_ij - eps_j A_j B_ji| over 64x64 tile pairs
+// REF reciprocity residual max |eps_i A_i B_ij - eps_j A_j B_ji| (eq. 4.4):
+// one workgroup per 64 x 64 tile pair (I, J), I <= J; the partner tile goes
+// through LDS so both are read as rows; the pair's maximum goes to blk[pair].
 __global__ void __launch_bounds__(256)
-ref_reciprocity(const double* __restrict__ B, long ldb, int n, const double* __restrict__ eps,
-                const double* __restrict__ area, Scalars* sc) {
+ref_reciprocity(const double* __restrict__ B, long ldb, int n, int t, const double* __restrict__ eps,
+                const double* __restrict__ area, double* __restrict__ blk) {
   __shared__ double sT[64][65];
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (J < I) return;
+  __shared__ double wI[64], wJ[64];
+  __shared__ double red[4];
+  int I, J;
+  pair_from_index(blockIdx.x, t, I, J);
   const int tid = threadIdx.x, c = tid & 63, rg = tid >> 6;
-  for (int m = 0; m < 16; ++m) {
-    int r = rg + 4 * m;
-    int i = J * 64 + r, j = I * 64 + c;
-    sT[r][c] = (i < n && j < n) ? eps[i] * area[i] * B[static_cast<long>(i) * ldb + j] : 0.0;
+  if (tid < 64) {
+    const int i = I * 64 + tid;
+    wI[tid] = i < n ? eps[i] * area[i] : 0.0;
+  } else if (tid < 128) {
+    const int j = J * 64 + tid - 64;
+    wJ[tid - 64] = j < n ? eps[j] * area[j] : 0.0;
+  }
+  double v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {  // partner tile (J, I)
+    const int i = J * 64 + rg + 4 * m, j = I * 64 + c;
+    v[m] = (i < n && j < n) ? B[static_cast<long>(i) * ldb + j] : 0.0;
+  }
+  double u[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {  // own tile (I, J)
+    const int i = I * 64 + rg + 4 * m, j = J * 64 + c;
+    u[m] = (i < n && j < n) ? B[static_cast<long>(i) * ldb + j] : 0.0;
   }
   __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 16; ++m) sT[rg + 4 * m][c] = wJ[rg + 4 * m] * v[m];
+  __syncthreads();
   double mx = 0.0;
+#pragma unroll
   for (int m = 0; m < 16; ++m) {
-    int r = rg + 4 * m;
-    int i = I * 64 + r, j = J * 64 + c;
-    if (i < n && j < n) {
-      double g = eps[i] * area[i] * B[static_cast<long>(i) * ldb + j];
-      mx = fmax(mx, fabs(g - sT[c][r]));
-    }
+    const int r = rg + 4 * m;
+    mx = fmax(mx, fabs(wI[r] * u[m] - sT[c][r]));
   }
-  block_max(mx, &sc->red[1]);
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if (c == 0) red[rg] = mx;
+  __syncthreads();
+  if (tid == 0) blk[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-__global__ void copy_scalars_out(const Scalars* sc, double* out) {
+// out[0] = max of the closure block maxima, out[1] = of the reciprocity ones
+__global__ void __launch_bounds__(256)
+ref_final(const double* __restrict__ bc, int nc, const double* __restrict__ br, long nr, double* __restrict__ out) {
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nc; q += 256) a = fmax(a, bc[q]);
+  for (long q = threadIdx.x; q < nr; q += 256) b = fmax(b, br[q]);
+  for (int off = 32; off > 0; off >>= 1) {
+    a = fmax(a, __shfl_xor(a, off));
+    b = fmax(b, __shfl_xor(b, off));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = sc->red[0];
-    out[1] = sc->red[1];
+    out[0] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+    out[1] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
   }
 }
 
