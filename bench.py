@@ -374,8 +374,9 @@ def run_batch64(args) -> int:
     pairs), two bands each (IR eps, solar alpha), 1e4 rays per face: one step
     restores every noisy F and runs the whole batch - enforcement of every
     instance (FRACVAR, each stops on the device at closure defect <= 1e-13),
-    then LU + solves of all 128 REF matrices - replayed from one captured CUDA
-    graph.  Two Gebhart variants are timed: FP64, and FP32 with one FP64
+    then LU + solves of all 128 REF matrices - replayed from a captured CUDA
+    graph; --inflight k keeps k steps in flight (k graphs over their own
+    buffers, each replayed on its own stream).  Two Gebhart variants are timed: FP64, and FP32 with one FP64
     refinement step; the line reports the faster one whose error on the
     three smallest instances is within 1e-10 of the oracle (or the one named
     by --precision)."""
@@ -410,14 +411,19 @@ def run_batch64(args) -> int:
     order = np.argsort([i.n for i in insts])[:3]
     ref_cache = {}
     results = {}
+    nslots = max(1, args.inflight)
+    # one set of models (own F copies and outputs) per step in flight
+    slot_models = [models] + [[{"F": f.clone(), "area": m["area"], "n_rays": m["n_rays"], "eps": m["eps"],
+                                "rho": m["rho"]} for m, f in zip(models, f0)] for _ in range(nslots - 1)]
     for name in wanted:
         prec, ir = variants[name]
-        batch = rad.Batch(models, precision=prec)
+        batches = [rad.Batch(ms_, precision=prec) for ms_ in slot_models]
+        batch = batches[0]
 
-        def step():
-            for m, f in zip(models, f0):
+        def step(k=0):
+            for m, f in zip(slot_models[k], f0):
                 m["F"].copy_(f)
-            batch.run(enforce_iters=iters, enforce_tol=1e-13, ir_steps=ir)
+            batches[k].run(enforce_iters=iters, enforce_tol=1e-13, ir_steps=ir)
 
         step()
         torch.cuda.synchronize()
@@ -432,22 +438,42 @@ def run_batch64(args) -> int:
                 if (k, b) not in ref_cache:
                     ref_cache[(k, b)] = oracle.gebhart_ref(fk, insts[k].eps[b], insts[k].rho[b])
                 errs.append(float(np.abs(batch.B[k][b].cpu().numpy() - ref_cache[(k, b)]).max()))
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step()
-        for _ in range(args.warmup):
-            g.replay()
+        # one captured graph per slot, each replayed on its own stream
+        streams = [torch.cuda.Stream() for _ in range(nslots)]
+        graphs = []
+        for k in range(nslots):
+            streams[k].wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(streams[k]):
+                step(k)  # warm-up on the capture stream
+            torch.cuda.current_stream().wait_stream(streams[k])
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=streams[k]):
+                step(k)
+            graphs.append(g)
+
+        def replay(i):
+            with torch.cuda.stream(streams[i % nslots]):
+                graphs[i % nslots].replay()
+
+        def fork_join(join):
+            for s_ in streams:
+                if join:
+                    torch.cuda.current_stream().wait_stream(s_)
+                else:
+                    s_.wait_stream(torch.cuda.current_stream())
+
+        fork_join(False)
+        for i in range(args.warmup):
+            replay(i)
+        fork_join(True)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.steps):
-            g.replay()
+        fork_join(False)
+        for i in range(args.steps):
+            replay(i)
+        fork_join(True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
@@ -455,7 +481,7 @@ def run_batch64(args) -> int:
                          "max_abs_err_vs_oracle_smallest3": max(errs)}
         log(f"[{name}] {ms:.2f} ms per step, {128e3 / ms:.1f} REF/s, max|B - B_oracle| on the 3 smallest "
             f"instances x 2 bands: {max(errs):.3e}")
-        del g, batch
+        del graphs, batches, batch
         torch.cuda.synchronize()
     ok = [k for k in wanted if results[k]["max_abs_err_vs_oracle_smallest3"] <= 1e-10]
     choice = min(ok or wanted, key=lambda k: results[k]["ms_per_step"])
@@ -468,7 +494,8 @@ def run_batch64(args) -> int:
         "vs_baseline": None, "dtype": "f64" if choice == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": "batch64: 64 models, N log-uniform [256, 4096], 2 bands, 1e4 rays/face",
                    "sum_n": int(sum(i.n for i in insts)), "enforce_iters_max": iters, "enforce_tol": 1e-13,
-                   "precision": choice, "ir_steps": variants[choice][1], "graph": True},
+                   "precision": choice, "ir_steps": variants[choice][1], "graph": True,
+                   "steps_in_flight": nslots},
         "variants": results,
         # LU (2/3 N^3) + two bands of N x (N+1) solves (2 N^2 (N+1) each), per step
         "solve_flops_per_step": sum(2.0 / 3.0 * i.n ** 3 + 2 * 2.0 * i.n * i.n * (i.n + 1) for i in insts),

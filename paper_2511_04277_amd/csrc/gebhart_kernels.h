@@ -494,9 +494,14 @@ copy_block(const S* __restrict__ src, long lds, int n, D* __restrict__ dst, long
     dst[static_cast<long>(i) * ldd + j] = static_cast<D>(src[static_cast<long>(i) * lds + j]);
 }
 
+// max of v over a 256-thread block, merged into *target with one atomic per
+// block (every thread of the block must call it)
 __device__ inline void block_max(double v, double* target) {
+  __shared__ double red[4];
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(target, v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) atomic_max_nonneg(target, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
 // R = E - X  (rows < n, cols <= n), E from F and eps on the fly
