@@ -805,8 +805,7 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
                            ei, pair_start, C, it == 0 ? 1 : 0);
       }
       hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fin)), dim3(256), 0, s, ei,
-                         fin_start, C);
-      hipLaunchKernelGGL(enf_decide_batched, dim3(static_cast<unsigned>(C)), dim3(256), 0, s, ei, enforce_tol);
+                         fin_start, C, enforce_tol);
     }
     hipLaunchKernelGGL(enf_apply_scale_batched, dim3(static_cast<unsigned>(P->total_rows)), dim3(256), 0, s, ei,
                        row_start, C);

@@ -13,7 +13,8 @@
 //              also carry the space column.
 //   finalize : s_i = sum of the partials in fixed tile order (reproducible),
 //              stores 1/s_i, closure defect max |s_i - 1|.
-//   decide   : convergence flag and statistics (device-side, no host sync).
+//   decide   : convergence flag and statistics (device-side, no host sync),
+//              by the finalize block that finishes last.
 // The last closure scale is applied by a final streaming pass.
 #include "enforce_kernels.h"
 
@@ -109,8 +110,7 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
         hipLaunchKernelGGL(enf_sweep, dim3(static_cast<unsigned>(pairs)), dim3(ENF_THREADS), 0, s, in,
                            it == 0 ? 1 : 0);
       }
-      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(fin_blocks(n))), dim3(256), 0, s, in);
-      hipLaunchKernelGGL(enf_decide, dim3(1), dim3(256), 0, s, in, tol);
+      hipLaunchKernelGGL(enf_finalize, dim3(static_cast<unsigned>(fin_blocks(n))), dim3(256), 0, s, in, tol);
     }
     RAD_HIP_CHECK(hipGetLastError());
     launched += nb;

@@ -18,7 +18,7 @@ struct EnfCtrl {
   int status;        // device-raised status (0 ok, negative error)
   int converged;     // 1 once the tolerance is met
   int iters;         // iterations executed
-  int pad;
+  int done;          // finalize blocks of the current iteration that finished
   double last_defect, last_recip;
 };
 
@@ -287,12 +287,57 @@ enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair
   enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);
 }
 
-// Row sums s_i of the (t + 1) partials of each row: 8 lanes per row take
-// every 8th partial, then combine over the lane masks 1, 2, 4 (fixed order).
+// finalize blocks (FIN_ROWS rows each), declared ahead of the decide step
 constexpr int FIN_LANES = 8;
 constexpr int FIN_ROWS = 256 / FIN_LANES;  // rows per 256-thread block
 
-__device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks) {
+// Iteration count, closure defect, reciprocity error and the stop flag from
+// the finalize blocks' maxima, run by the instance's last finalize block.
+__device__ __forceinline__ void enf_decide_body(const EnfInst& in, double tol) {
+  EnfCtrl* ctrl = in.ctrl;
+  if (ctrl->converged || ctrl->status < 0) return;
+  const int nf = (in.n + FIN_ROWS - 1) / FIN_ROWS;
+  double d = 0.0, rm = 0.0, em = 0.0;
+  for (int b = threadIdx.x; b < nf; b += blockDim.x) {
+    d = fmax(d, in.finred[3 * b]);
+    rm = fmax(rm, in.finred[3 * b + 1]);
+    em = fmax(em, in.finred[3 * b + 2]);
+  }
+  __shared__ double fr[3][4];
+  for (int off = 32; off > 0; off >>= 1) {
+    d = fmax(d, __shfl_xor(d, off));
+    rm = fmax(rm, __shfl_xor(rm, off));
+    em = fmax(em, __shfl_xor(em, off));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    fr[0][w] = d;
+    fr[1][w] = rm;
+    fr[2][w] = em;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) {
+      d = fmax(d, fr[0][q]);
+      rm = fmax(rm, fr[1][q]);
+      em = fmax(em, fr[2][q]);
+    }
+    d = fmax(d, fr[0][0]);
+    rm = fmax(rm, fr[1][0]);
+    em = fmax(em, fr[2][0]);
+    ctrl->iters += 1;
+    ctrl->last_defect = d;
+    ctrl->last_recip = em > 0.0 ? rm / em : 0.0;
+    if (tol > 0.0 && d <= tol) ctrl->converged = 1;
+  }
+}
+
+// Row sums s_i of the (t + 1) partials of each row: 8 lanes per row take
+// every 8th partial, then combine over the lane masks 1, 2, 4 (fixed order).
+// Each block's maxima go to finred; the block that finishes last (a counter
+// in the control block, one atomic per block) reduces them and decides.
+
+__device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks, double tol) {
   const int n = in.n, t = in.t;
   const double* __restrict__ partial = in.partial;
   double* __restrict__ scale = in.scale;  // receives 1 / s_i
@@ -336,76 +381,38 @@ __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, in
     fr[2][w] = em;
   }
   __syncthreads();
+  __shared__ int last;
   if (threadIdx.x == 0) {
     for (int c = 0; c < 3; ++c) {
       double x = fr[c][0];
       for (int q = 1; q < 4; ++q) x = fmax(x, fr[c][q]);
       in.finred[3 * static_cast<long>(blk) + c] = x;
     }
+    __threadfence();  // the maxima are visible before the block counts itself done
+    last = atomicAdd(&ctrl->done, 1) == nblocks - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) ctrl->done = 0;
+    enf_decide_body(in, tol);
   }
 }
 
 inline long fin_blocks(int64_t n) { return ceil_div(n, FIN_ROWS); }
 
-__global__ void __launch_bounds__(256) enf_finalize(EnfInst in) {
-  enf_finalize_body(in, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(256) enf_finalize(EnfInst in, double tol) {
+  enf_finalize_body(in, blockIdx.x, gridDim.x, tol);
 }
 
 // blocks [blk_start[k], blk_start[k+1]) are the FIN_ROWS-row blocks of instance k
 __global__ void __launch_bounds__(256)
-enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count) {
+enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count, double tol) {
   const int k = find_segment(blk_start, count, blockIdx.x);
   const int nb = static_cast<int>(blk_start[k + 1] - blk_start[k]);
-  enf_finalize_body(ins[k], static_cast<int>(blockIdx.x - blk_start[k]), nb);
+  enf_finalize_body(ins[k], static_cast<int>(blockIdx.x - blk_start[k]), nb, tol);
 }
 
-// Iteration count, closure defect, reciprocity error and the stop flag from
-// the finalize blocks' maxima (one 256-thread block per instance).
-__device__ __forceinline__ void enf_decide_body(const EnfInst& in, double tol) {
-  EnfCtrl* ctrl = in.ctrl;
-  if (ctrl->converged || ctrl->status < 0) return;
-  const int nf = (in.n + FIN_ROWS - 1) / FIN_ROWS;
-  double d = 0.0, rm = 0.0, em = 0.0;
-  for (int b = threadIdx.x; b < nf; b += blockDim.x) {
-    d = fmax(d, in.finred[3 * b]);
-    rm = fmax(rm, in.finred[3 * b + 1]);
-    em = fmax(em, in.finred[3 * b + 2]);
-  }
-  __shared__ double fr[3][4];
-  for (int off = 32; off > 0; off >>= 1) {
-    d = fmax(d, __shfl_xor(d, off));
-    rm = fmax(rm, __shfl_xor(rm, off));
-    em = fmax(em, __shfl_xor(em, off));
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    fr[0][w] = d;
-    fr[1][w] = rm;
-    fr[2][w] = em;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < 4; ++q) {
-      d = fmax(d, fr[0][q]);
-      rm = fmax(rm, fr[1][q]);
-      em = fmax(em, fr[2][q]);
-    }
-    d = fmax(d, fr[0][0]);
-    rm = fmax(rm, fr[1][0]);
-    em = fmax(em, fr[2][0]);
-    ctrl->iters += 1;
-    ctrl->last_defect = d;
-    ctrl->last_recip = em > 0.0 ? rm / em : 0.0;
-    if (tol > 0.0 && d <= tol) ctrl->converged = 1;
-  }
-}
-
-__global__ void __launch_bounds__(256) enf_decide(EnfInst in, double tol) { enf_decide_body(in, tol); }
-
-// one block per instance
-__global__ void __launch_bounds__(256) enf_decide_batched(const EnfInst* __restrict__ ins, double tol) {
-  enf_decide_body(ins[blockIdx.x], tol);
-}
 
 __device__ __forceinline__ void enf_apply_scale_body(const EnfInst& in, long row) {
   if (in.ctrl->status < 0 || in.ctrl->iters == 0) return;
@@ -446,7 +453,7 @@ __device__ __forceinline__ void enf_init_body(EnfCtrl* ctrl) {
     ctrl->status = 0;
     ctrl->converged = 0;
     ctrl->iters = 0;
-    ctrl->pad = 0;
+    ctrl->done = 0;
     ctrl->last_defect = ctrl->last_recip = 0.0;
   }
 }
