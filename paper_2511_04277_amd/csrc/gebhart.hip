@@ -95,10 +95,10 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
         RAD_GEMM(u, false);
       }
     }
-    // the previous panel's far update must be done before this panel's rows
-    // to the right are eliminated
+    // the previous panel's far update must have reached this panel's rows
+    // before they are eliminated (its first row chunks; event ev[3])
     if (c0 > 0) {
-      e = stream_wait(s, s2, ss->ev[1]);
+      e = hipStreamWaitEvent(s, ss->ev[3], 0);
       if (e != hipSuccess) return e;
     }
     // (2) the panel's rows to the right of the panel: block forward substitution
@@ -110,6 +110,12 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
                             ldk, f.np - c1);
       if (Y) gemm_add_segment<T>(u, Y + static_cast<long>(k0) * ldy, ldy, Y + static_cast<long>(r1) * ldy, ldy, wy);
       if (u.nseg) RAD_GEMM(u, false);
+    }
+    // the rest of the previous panel's far update must be done before the
+    // next panel's columns take this panel's update
+    if (c0 > 0) {
+      e = stream_wait(s, s2, ss->ev[1]);
+      if (e != hipSuccess) return e;
     }
     // (3) everything below and right of the panel: K = panel-width GEMMs,
     // the next panel's columns on s, the rest on s2
@@ -134,6 +140,7 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
           const int tx = gemm_tiles<T>(v) / ((v.M + GEMM_TILE - 1) / GEMM_TILE);  // column tiles
           rows = std::max(1, chunk_tiles / std::max(1, tx)) * GEMM_TILE;
         }
+        bool marked = false;
         for (int r0 = 0; r0 < v.M; r0 += rows) {
           GemmArgs<T> vc = v;
           vc.A = v.A + static_cast<long>(r0) * ldk;
@@ -141,7 +148,18 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
           for (int q = 0; q < vc.nseg; ++q) vc.C[q] = v.C[q] + static_cast<long>(r0) * v.ldc[q];
           hipError_t ge = launch_gemm(vc, false, s2);
           if (ge != hipSuccess) return ge;
+          // the next panel's rows (the first NB2 rows) are done: its forward
+          // substitution may start while the rest is updated
+          if (!marked && r0 + vc.M >= std::min(NB2, v.M)) {
+            ge = hipEventRecord(ss->ev[3], s2);
+            if (ge != hipSuccess) return ge;
+            marked = true;
+          }
         }
+      }
+      if (!v.nseg) {  // nothing beyond the next panel: its rows are ready once s2 is
+        e = hipEventRecord(ss->ev[3], s2);
+        if (e != hipSuccess) return e;
       }
     }
   }
