@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X dense MFMA
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "int8": 5000.0}  # MI355X dense MFMA (int8: TOP/s)
+I8X_PRODUCTS = 28  # digit products per emulated FP64 product (7 digits per operand, pairs s + t < 7)
 PEAK_HBM_GBS = 8000.0
 SIGMA = 5.67e-8
 T_SPACE = 3.0
@@ -86,10 +87,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["auto", "fp64", "fp32_ir1", "fp32_ir"], default="auto",
+    ap.add_argument("--precision", choices=["auto", "fp64", "fp64_i8", "fp32_ir1", "fp32_ir"], default="auto",
                     help="Gebhart variant of the step (auto: the fastest within 1e-10 of the oracle)")
     ap.add_argument("--solve-reps", type=int, default=3)
-    ap.add_argument("--solve-variants", default="fp64,fp32_ir1,fp32_ir",
+    ap.add_argument("--solve-variants", default="fp64,fp64_i8,fp32_ir1,fp32_ir",
                     help="comma list of Gebhart variants timed alone and checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--inflight", type=int, default=2,
@@ -161,10 +162,11 @@ def main() -> int:
     torch.cuda.synchronize()
     del Fcal
 
-    # ---- Gebhart alone: FP64, and FP32 + FP64 refinement ------------------
-    # FP32+IR with one refinement step (its error is measured against the
-    # oracle below) and refined until the correction is <= 1e-12
-    variants = {"fp64": ("fp64", 0.0, 0), "fp32_ir1": ("fp32_ir", 1.0, 1), "fp32_ir": ("fp32_ir", 1e-12, 4)}
+    # ---- Gebhart alone: FP64, FP64 with int8 digit products, FP32 + FP64
+    # refinement (one step, whose error is measured against the oracle
+    # below, and refined until the correction is <= 1e-12)
+    variants = {"fp64": ("fp64", 0.0, 0), "fp64_i8": ("fp64_i8", 0.0, 0), "fp32_ir1": ("fp32_ir", 1.0, 1),
+                "fp32_ir": ("fp32_ir", 1e-12, 4)}
     chosen = [v for v in args.solve_variants.split(",") if v]
     if args.precision != "auto" and args.precision not in chosen:
         chosen.append(args.precision)
@@ -205,7 +207,8 @@ def main() -> int:
     else:
         choice = min(ok or list(solve), key=lambda v: solve[v]["ms"])
     for v in solve:
-        peak = PEAK_TFLOPS["fp64" if solve[v]["precision"] == "fp64" else "fp32"]
+        # FP64-equivalent rate against the FP64 peak (int8 digit products too)
+        peak = PEAK_TFLOPS["fp32" if solve[v]["precision"] == "fp32_ir" else "fp64"]
         solve[v]["solve_tflops"] = solve_flops(n) / (solve[v]["ms"] * 1e-3) / 1e12
         solve[v]["solve_frac_of_peak"] = solve[v]["solve_tflops"] / peak
     prec, ir_tol, ir_max = variants[choice]
@@ -262,7 +265,7 @@ def main() -> int:
         t_lat.append(e0.elapsed_time(e1))
     latency_ms = min(t_lat)
     NK = len(L.PROFILE_KINDS)
-    dom = "gemm_f64" if prec == "fp64" else "gemm_f32"
+    dom = {"fp64": "gemm_f64", "fp64_i8": "gemm_i8x"}.get(prec, "gemm_f32")
     # one more untimed step with every profiled kernel kind bracketed by events:
     # the per-kind breakdown (an event pair costs several microseconds, so the
     # timed steps bracket only the dominant kernel)
@@ -303,9 +306,16 @@ def main() -> int:
                           "gbs": (p.bytes / (p.total_ms * 1e-3) / 1e9) if p.bytes else None}
     pk = profs[L.PROFILE_KINDS.index(dom)]
     achieved = pk.flops / pk.launches / (pk.total_ms / pk.launches * 1e-3) / 1e12
-    peak = PEAK_TFLOPS["fp64" if dom == "gemm_f64" else "fp32"]
-    kname = f"gemm_lds<{'double' if dom == 'gemm_f64' else 'float'}, false>"
-    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    extra = {}
+    if dom == "gemm_i8x":
+        # the kernel's own arithmetic: 28 int8 digit products per FP64 product
+        extra["fp64_equivalent_tflops"] = achieved
+        achieved *= I8X_PRODUCTS
+        peak, unit, kname = PEAK_TFLOPS["int8"], "TOP/s", "emu_gemm<7>"
+    else:
+        peak, unit = PEAK_TFLOPS["fp64" if dom == "gemm_f64" else "fp32"], "TFLOP/s"
+        kname = f"gemm_lds<{'double' if dom == 'gemm_f64' else 'float'}, false>"
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": unit, **extra,
                 "frac": achieved / peak, "traffic": measured_traffic(kname, prec),
                 "algorithmic_bytes_per_launch": pk.bytes / pk.launches,
                 "flops_per_launch": pk.flops / pk.launches, "avg_launch_us": 1000.0 * pk.total_ms / pk.launches,
@@ -351,7 +361,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp64_i8": "f64+i8"}.get(prec, "f32+f64"),
         "data": "synthetic",
         "config": {"workload": "open_box_n8192 (1x1x0.25 m, 1/64 m cells, 1e4 rays/face) full pipeline",
                    "n": n, "precision": prec, "ir_steps_max": ir_max, "kappa": "fracvar", "enforce_tol": ENF_TOL,

@@ -54,6 +54,10 @@ extern "C" {
 #define RAD_PREC_FP64 0       /* FP64 MFMA factorization and solves          */
 #define RAD_PREC_FP32_IR 1    /* FP32 MFMA factorization and solves, FP64
                                  residual iterative refinement               */
+#define RAD_PREC_FP64_I8 2    /* FP64 factorization and solves whose panel-
+                                 width products run on the int8 matrix cores
+                                 as exact digit products (7 digits of 7 bits
+                                 per operand, FP64 accumulation)             */
 
 /* Per-call statistics (host struct). */
 typedef struct rad_stats {
@@ -114,9 +118,14 @@ int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const double* area,
  * opaque faces).  K is strictly diagonally dominant by rows when rho < 1 and
  * the rows of F sum to <= 1, so the factorization is a block LU without
  * pivoting.
- * precision: RAD_PREC_FP64, or RAD_PREC_FP32_IR (FP32 factorization/solves,
+ * precision: RAD_PREC_FP64, RAD_PREC_FP32_IR (FP32 factorization/solves,
  *   refinement B += K^{-1}(E - K B) with the residual in FP64 until
- *   max|delta| <= ir_tol or ir_max steps; RAD_WNOTCONVERGED otherwise).
+ *   max|delta| <= ir_tol or ir_max steps; RAD_WNOTCONVERGED otherwise), or
+ *   RAD_PREC_FP64_I8 (FP64 factors and solves; the K = 1024 trailing,
+ *   substitution and back-substitution products are exact int8 digit
+ *   products with FP64 accumulation, rounding about 2^-49 relative to the
+ *   operand row maxima; ir_tol / ir_max ignored).  The factors of FP64_I8
+ *   are FP64 factors (same size as RAD_PREC_FP64).
  * factors: caller-owned, >= rad_gebhart_factor_bytes(n, precision); receives
  *   the factorization, which rad_gebhart_ref_adjoint reuses.  It stays valid
  *   until the caller frees or overwrites it.
@@ -303,7 +312,9 @@ int32_t rad_tuning_set(const rad_tuning* in);
 #define RAD_PROF_AGGREGATE 4     /* aggregation reduction                            */
 #define RAD_PROF_GEMM_F64_T 5    /* FP64 MFMA GEMM with transposed A (adjoint)       */
 #define RAD_PROF_GEMM_F32_T 6    /* FP32 MFMA GEMM with transposed A (adjoint)       */
-#define RAD_PROF_KINDS 7
+#define RAD_PROF_GEMM_I8X 7      /* FP64 product emulated with int8 MFMA digit products */
+#define RAD_PROF_I8X_SPLIT 8     /* operand scaling and digit split for those products */
+#define RAD_PROF_KINDS 9
 
 typedef struct rad_kernel_profile {
   int64_t launches;

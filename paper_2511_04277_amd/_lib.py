@@ -25,6 +25,7 @@ RAD_KAPPA_FRACVAR = 0
 RAD_KAPPA_HALF = 1
 RAD_PREC_FP64 = 0
 RAD_PREC_FP32_IR = 1
+RAD_PREC_FP64_I8 = 2
 
 
 class RadStats(ctypes.Structure):
@@ -79,7 +80,7 @@ class RadTuning(ctypes.Structure):
 
 
 PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate", "gemm_f64_t",
-                 "gemm_f32_t"]
+                 "gemm_f32_t", "gemm_i8x", "i8x_split"]
 
 
 class RadError(RuntimeError):

@@ -15,7 +15,7 @@ import torch
 from . import _lib as L
 
 _KAPPA = {"fracvar": L.RAD_KAPPA_FRACVAR, "half": L.RAD_KAPPA_HALF}
-_PREC = {"fp64": L.RAD_PREC_FP64, "fp32_ir": L.RAD_PREC_FP32_IR}
+_PREC = {"fp64": L.RAD_PREC_FP64, "fp32_ir": L.RAD_PREC_FP32_IR, "fp64_i8": L.RAD_PREC_FP64_I8}
 
 
 def _vp(t: Optional[torch.Tensor]):

@@ -1,0 +1,306 @@
+// FP64 matrix products emulated on the int8 matrix cores (gfx950).
+//
+//   C[seg] += alpha * A * B,   A: M x K,  B: K x N,  C FP64
+//
+// Error-free splitting (Ozaki's scheme): each k block of 64 of every row r
+// of an operand (a row of A, a column of B) is scaled by the power of two
+// sigma_r,kb > max_{k in kb} |X_rk| and written as S signed 7-bit digits,
+//
+//   X_rk = sigma_r,kb * sum_{s<S} d_s(r,k) 2^{-7(s+1)} + t_rk,  |d_s| <= 127,
+//   |t_rk| < sigma_r,kb 2^{-7S},
+//
+// each step (scale by 128, truncate, subtract) exact in FP64.  Products of
+// digit matrices D^A_s D^B_t over one k block are exact in int32
+// (v_mfma_i32_16x16x64_i8); the pairs with s + t >= S are dropped, the kept
+// pairs are summed in int32 by class d = s + t, weighted by 2^{-7(d+2)} in
+// FP64 and added to FP64 accumulators with the block's sigma^A_i sigma^B_j.
+// Per element and k block the result differs from the exact product by less
+// than
+//   (S + 3) 64 sigma^A_i,kb sigma^B_j,kb 2^{-7S}
+// (the two tails and the dropped pairs) plus FP64 accumulation rounding; with
+// S = 7 that is 2^-49 per unit of 64 sigma^A sigma^B as a worst case, and in
+// practice (errors of random sign) a few hundred FP64 ulps of the product.
+//
+// Digit layout (written by emu_split, read by emu_gemm): operand rows padded
+// to a multiple of 64 (T tiles) and k to 64 nkb.  The 64 rows x S slices x
+// 64 k of k block kb of row tile rt are block kb T + rt, S * 256 chunks of 16
+// bytes, laid out exactly as the GEMM keeps them in LDS: chunk c
+// (k 16c..16c+15) of row rr of slice s at position emu_lds_idx(s, rr, c), so
+// the GEMM stages a block with straight 1 KB global-to-LDS copies.  Padding
+// digits are zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gemm.h"
+
+namespace rad {
+
+constexpr int EMU_S = 7;          // digits per operand element
+constexpr int EMU_TILE = 64;      // C tile of one workgroup (64 x 64)
+constexpr int EMU_KB = 64;        // k per stage (one MFMA 16 x 16 x 64)
+constexpr int EMU_THREADS = 256;  // four waves, 32 x 32 of C each
+
+typedef int emu_v4i __attribute__((ext_vector_type(4)));
+
+// ---- operand scaling and splitting -------------------------------------
+
+// LDS position of 16-byte chunk c of row r of slice s in a 64-row block.
+// The chunk index is XOR-swizzled with row bits so that the 16 (or 8) lanes
+// of one ds_read_b128 phase, which read rows r..r+15 at one chunk, hit
+// distinct banks.
+__device__ __forceinline__ int emu_lds_idx(int s, int r, int c) {
+  return ((s * EMU_TILE + r) << 2) + (c ^ (((r >> 1) ^ (r >> 2)) & 3));
+}
+
+
+// Operand access: row r < R0 is element (r, k) at X[0][r sr[0] + k sk[0]],
+// row R0 <= r < R at X[1][(r - R0) sr[1] + k sk[1]]; both segments have the
+// same orientation (k contiguous, or rows contiguous).  Rows r >= R and
+// k >= K of the padded range read as zero.
+struct EmuOperand {
+  const double* X[2];
+  long sr[2], sk[2];
+  int R0, R, K;
+};
+
+__device__ __forceinline__ double emu_load(const EmuOperand& op, int r, int k) {
+  if (r >= op.R || k >= op.K) return 0.0;
+  const int q = r >= op.R0;
+  const long rr = r - (q ? op.R0 : 0);
+  return op.X[q][rr * op.sr[q] + static_cast<long>(k) * op.sk[q]];
+}
+
+// Scale and digits of one 64-row x 64-k block per workgroup.  The block's
+// doubles are read with 512-byte contiguous loads in whichever orientation the
+// operand has and transposed through LDS; thread t takes 16 consecutive k of
+// row t / 4 (chunk c = t % 4), the four threads of a row agree on the row's
+// maximum, the one with chunk 0 writes sigma, and a wave's stores of one
+// slice are one contiguous 1 KB piece of the block.
+template <int S, bool KC>
+__global__ __launch_bounds__(256) void emu_split(EmuOperand op, double* __restrict__ sig, int8_t* __restrict__ out) {
+  __shared__ double tile[EMU_TILE][EMU_KB + 1];
+  const int rt = blockIdx.x, kb = blockIdx.y;
+  const int t = threadIdx.x;
+  const int r0 = rt * EMU_TILE, k0 = kb * EMU_KB;
+#pragma unroll
+  for (int it = 0; it < EMU_TILE * EMU_KB / 256; ++it) {
+    const int e = it * 256 + t;
+    const int row = KC ? e / EMU_KB : e % EMU_TILE;
+    const int k = KC ? e % EMU_KB : e / EMU_TILE;
+    tile[row][k] = emu_load(op, r0 + row, k0 + k);
+  }
+  __syncthreads();
+  const int row = t >> 2, c = t & 3;
+  double x[16], m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    x[i] = tile[row][c * 16 + i];
+    m = fmax(m, fabs(x[i]));
+  }
+  m = fmax(m, __shfl_xor(m, 1));
+  m = fmax(m, __shfl_xor(m, 2));
+  int ex = 0;
+  if (m > 0.0) frexp(m, &ex);  // m = f 2^ex, f in [0.5, 1): m < 2^ex
+  const double sg = m > 0.0 ? ldexp(1.0, ex) : 1.0;
+  if (c == 0) sig[static_cast<long>(kb) * gridDim.x * EMU_TILE + r0 + row] = sg;
+  const double inv = 1.0 / sg;  // a power of two: exact
+  union {
+    emu_v4i v;
+    int8_t b[16];
+  } dg[S];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double a = x[i] * inv;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      a *= 128.0;
+      const double d = __builtin_trunc(a);
+      a -= d;
+      dg[s].b[i] = static_cast<int8_t>(static_cast<int>(d));
+    }
+  }
+  emu_v4i* blk = reinterpret_cast<emu_v4i*>(out) + (static_cast<long>(kb) * gridDim.x + rt) * S * 256;
+#pragma unroll
+  for (int s = 0; s < S; ++s) blk[emu_lds_idx(s, row, c)] = dg[s].v;
+}
+
+// ---- the product --------------------------------------------------------
+
+struct EmuGemmArgs {
+  const int8_t* A;   // digits of A: mt 64-row tiles per k block
+  const double* sa;  // scales of A per k block and row ([kb][64 mt])
+  const int8_t* B;   // digits of B^T (rows = columns of C): nt tiles per k block
+  const double* sb;  // scales of B per k block and column ([kb][64 nt])
+  int mt, nt, nkb;
+  int ty0, nty;      // the launch covers A tiles [ty0, ty0 + nty) ...
+  int tx0, ntx;      // ... times B tiles [tx0, tx0 + ntx)
+  int M;             // rows i < M of C are written
+  double alpha;
+  int nseg;          // column j < N[0]: C[0][i ldc[0] + j]; else C[1][i ldc[1] + j - N[0]]
+  int N[2];
+  double* C[2];
+  long ldc[2];
+};
+
+// One 64 x 64 tile of C per workgroup, two workgroups per CU (64 KB of LDS
+// each, at most 256 registers per lane).  Per k block: the block's digits
+// arrive in LDS by global-to-LDS copies, every wave reads all its fragments
+// (S slices x 2 row blocks of A, S x 2 column blocks of B) into registers, the
+// LDS is released and the next block's copies start, and the MFMAs run from
+// registers meanwhile.  The digit pairs are taken class by class (d = s + t)
+// into one of two int32 accumulator sets, and each finished class is added to
+// the FP64 accumulators with its weight 2^{-7(d+2)} while the next class's
+// MFMAs run.
+template <int S>
+__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
+  constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
+  __shared__ emu_v4i lds[2][CH];        // [A, B][chunk]
+  int bx, by;
+  grouped_tile(xcd_contiguous(blockIdx.x, g.ntx * g.nty), g.ntx, g.nty, TILE_GROUP, bx, by);
+  bx += g.tx0;
+  by += g.ty0;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const emu_v4i* ga = reinterpret_cast<const emu_v4i*>(g.A) + static_cast<long>(by) * CH;
+  const emu_v4i* gb = reinterpret_cast<const emu_v4i*>(g.B) + static_cast<long>(bx) * CH;
+  const long stride_a = static_cast<long>(g.mt) * CH;  // chunks per k block
+  const long stride_b = static_cast<long>(g.nt) * CH;
+  // copies of one k block: wave w moves 1 KB pieces w, w + 4, ... of A then B
+  auto stage = [&](int kb) {
+    const emu_v4i* sa = ga + kb * stride_a;
+    const emu_v4i* sb = gb + kb * stride_b;
+#pragma unroll
+    for (int p = w; p < CH / 64; p += 4) {
+      __builtin_amdgcn_global_load_lds(sa + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[0][p * 64]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(sb + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[1][p * 64]), 16, 0, 0);
+    }
+  };
+  const int fr = l & 15, fc = l >> 4;
+  double acc[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+  stage(0);
+  for (int kb = 0; kb < g.nkb; ++kb) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    __syncthreads();                // and everyone else's
+    emu_v4i af[S][2], bf[S][2];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[s][i] = lds[0][emu_lds_idx(s, wr + 16 * i + fr, fc)];
+        bf[s][i] = lds[1][emu_lds_idx(s, wc + 16 * i + fr, fc)];
+      }
+    __syncthreads();  // every wave holds its fragments: the LDS is free
+    if (kb + 1 < g.nkb) stage(kb + 1);
+    // this block's scales of the lane's 8 rows and 2 columns
+    double sai[2][4], sbj[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      sbj[i] = g.sb[static_cast<long>(kb) * g.nt * EMU_TILE + bx * EMU_TILE + wc + 16 * i + fr];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        sai[i][v] = g.sa[static_cast<long>(kb) * g.mt * EMU_TILE + by * EMU_TILE + wr + 16 * i + 4 * fc + v];
+    }
+    double y[2][2][4];
+    // class d (pairs s + t = d) goes to int32 set d % 2; a finished pair of
+    // classes (d - 1, d) is folded as 128 acc_{d-1} + acc_d (exact: per k
+    // block |acc_d| <= 8 * 64 * 127^2, so the fold stays below 2^30) and added
+    // to the FP64 accumulators with weight 2^{-7(d+2)}
+    emu_v4i ci[2][2][2];
+    const emu_v4i zero = {0, 0, 0, 0};
+    auto flush = [&](int d, bool pair) {
+      const double wgt = ldexp(1.0, -7 * (d + 2));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int x = pair ? ci[0][i][j][v] * 128 + ci[1][i][j][v] : ci[d & 1][i][j][v];
+            y[i][j][v] = d == 1 ? static_cast<double>(x) * wgt : fma(static_cast<double>(x), wgt, y[i][j][v]);
+          }
+    };
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+#pragma unroll
+      for (int s = 0; s <= d; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            ci[d & 1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[s][i], bf[d - s][j], s == 0 ? zero : ci[d & 1][i][j], 0, 0, 0);
+      if (d & 1) flush(d, true);
+    }
+    if (S & 1) flush(S - 1, false);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] = fma(y[i][j][v], sai[i][v] * sbj[j], acc[i][j][v]);
+  }
+  // epilogue: lane l holds rows 4 (l / 16) + v, column l % 16 of each block
+  const int row0 = by * EMU_TILE + wr, col0 = bx * EMU_TILE + wc;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = col0 + 16 * j + fr;
+    int seg = 0, cc = col;
+    if (g.nseg > 1 && col >= g.N[0]) {
+      seg = 1;
+      cc = col - g.N[0];
+    }
+    if (cc >= g.N[seg] || seg >= g.nseg) continue;
+    double* Cc = g.C[seg] + cc;
+    const long ldc = g.ldc[seg];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + 16 * i + 4 * fc + v;
+        if (row >= g.M) continue;
+        double* p = Cc + static_cast<long>(row) * ldc;
+        *p = fma(g.alpha, acc[i][j][v], *p);
+      }
+  }
+}
+
+// ---- host side ------------------------------------------------------------
+
+// Bytes of the digits of an operand with R rows and K columns.
+inline size_t emu_digit_bytes(long R, long K) {
+  return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB) * EMU_KB * EMU_S;
+}
+
+// Scales and digits of one operand (kc: k contiguous in memory, else rows).
+// sig holds one entry per k block and padded row.
+inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, double* sig, hipStream_t s) {
+  const int T = (op.R + EMU_TILE - 1) / EMU_TILE;
+  const int nkb = (op.K + EMU_KB - 1) / EMU_KB;
+  if (T == 0 || nkb == 0) return hipSuccess;
+  if (kc)
+    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(T, nkb), dim3(256), 0, s, op, sig, dig);
+  else
+    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(T, nkb), dim3(256), 0, s, op, sig, dig);
+  return hipGetLastError();
+}
+
+// Entries of the scale array of an operand with R rows and K columns.
+inline size_t emu_scale_count(long R, long K) {
+  return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB);
+}
+
+inline hipError_t emu_launch(const EmuGemmArgs& g, hipStream_t s) {
+  if (g.ntx <= 0 || g.nty <= 0 || g.nkb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(emu_gemm<EMU_S>, dim3(g.ntx * g.nty), dim3(EMU_THREADS), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace rad

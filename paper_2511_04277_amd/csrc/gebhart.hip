@@ -28,10 +28,20 @@
 // refines in FP64:  R = E - K X = (E - X) + P X with P = F_sq diag(rho) (FP64
 // MFMA GEMM), delta = K^{-1} R with the FP32 factors, X += delta.
 //
+// RAD_PREC_FP64_I8 keeps FP64 factors and the FP64 chain, but the products
+// with K = panel width (the trailing update and forward substitution of each
+// panel, the back substitution's and the transposed solves' updates) run as
+// exact int8 digit products on the int8 matrix cores (emu_kernels.h): each
+// operand is scaled per row and split into 7 digits of 7 bits, and the digit
+// products are accumulated in FP64.
+//
 // Adjoint: K^T = U^T L^T, so Lambda = K^{-T} G is a block forward solve with
 // U^T (diagonal blocks D_k^{-T}) followed by a block backward solve with L^T,
 // both reusing the stored factors through transposed-A GEMMs; in FP32_IR mode
 // the residual G - K^T Lambda = (G - Lambda) + P^T Lambda is formed in FP64.
+#include <type_traits>
+
+#include "emu_kernels.h"
 #include "gebhart_kernels.h"
 
 namespace rad {
@@ -50,6 +60,100 @@ inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
   return gemm_args<T>(A, lda, M, K, T(-1), T(1));
 }
 
+// Digit buffers of the int8-emulated products (RAD_PREC_FP64_I8).  One set
+// serves every product of a solve: the products that use it run on the
+// caller's stream, except the side-stream part of a factorization panel's
+// update, which the next panel joins before it prepares its own operands.
+struct EmuWork {
+  int8_t* da;  // digits of op(A)
+  int8_t* db;  // digits of B^T
+  double* sa;  // scales of op(A) per k block and row
+  double* sb;  // scales of B per k block and column
+};
+
+// Scales and digits of both operands of C -= op(A) B; g receives the launch
+// arguments for all tiles (callers narrow them).  C(i, j) is C0[i ldc0 + j]
+// for j < N0 and C1[i ldc1 + j - N0] after.
+inline hipError_t emu_product(const EmuWork& e, const EmuOperand& oa, bool akc, const EmuOperand& ob, int M, int N0,
+                              double* C0, long ldc0, int N1, double* C1, long ldc1, EmuGemmArgs* g, hipStream_t s) {
+  {
+    ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0,
+                   (8.0 + EMU_S) * (static_cast<double>(oa.R) + ob.R) * static_cast<double>(oa.K));
+    hipError_t err = emu_prepare(oa, akc, e.da, e.sa, s);
+    if (err != hipSuccess) return err;
+    err = emu_prepare(ob, false, e.db, e.sb, s);
+    if (err != hipSuccess) return err;
+  }
+  const int mt = (oa.R + EMU_TILE - 1) / EMU_TILE, nt = (ob.R + EMU_TILE - 1) / EMU_TILE;
+  *g = EmuGemmArgs{e.da, e.sa, e.db, e.sb, mt, nt, (oa.K + EMU_KB - 1) / EMU_KB, 0, mt, 0, nt, M, -1.0,
+                   N1 > 0 ? 2 : 1, {N0, N1}, {C0, C1}, {ldc0, ldc1}};
+  return hipSuccess;
+}
+
+inline hipError_t emu_run(const EmuGemmArgs& g, int K, hipStream_t s) {
+  const double rows = std::max(0, std::min(g.M, (g.ty0 + g.nty) * EMU_TILE) - g.ty0 * EMU_TILE);
+  const double cols = std::max(0, std::min(g.N[0] + (g.nseg > 1 ? g.N[1] : 0), (g.tx0 + g.ntx) * EMU_TILE) -
+                                      g.tx0 * EMU_TILE);
+  ProfScope prof(s, RAD_PROF_GEMM_I8X, 2.0 * rows * cols * K, 8.0 * rows * cols * 2.0);
+  return emu_launch(g, s);
+}
+
+inline EmuOperand emu_operand(const double* X, long sr, long sk, int R, int K, const double* X1 = nullptr,
+                              long sr1 = 0, long sk1 = 0, int R1 = 0) {
+  return EmuOperand{{X, X1}, {sr, sr1}, {sk, sk1}, R, R + R1, K};
+}
+
+// Step (3) of a factorization panel with int8-emulated products: the panel's
+// L block (rows c1.., columns c0..c1) and its U block together with the
+// right-hand-side rows (rows c0..c1, columns c1.. of K then of Y) are split
+// once; the next panel's columns are updated on s, the rest on s2 in row
+// chunks, with the same events as the FP64 path.
+hipError_t factor_update_emu(const EmuWork& ew, const Fact<double>& f, int c0, int c1, int c2, double* Y, long ldy,
+                             int wy, hipStream_t s, hipStream_t s2, SideStream* ss) {
+  const long ldk = f.ldk;
+  double* kf = f.kf;
+  const int M = f.np - c1, K = c1 - c0, wyy = Y ? wy : 0;
+  EmuOperand oa = emu_operand(kf + static_cast<long>(c1) * ldk + c0, ldk, 1, M, K);
+  EmuOperand ob = emu_operand(kf + static_cast<long>(c0) * ldk + c1, 1, ldk, M, K,
+                              Y ? Y + static_cast<long>(c0) * ldy : nullptr, 1, ldy, wyy);
+  EmuGemmArgs g;
+  hipError_t e = emu_product(ew, oa, true, ob, M, M, kf + static_cast<long>(c1) * ldk + c1, ldk, wyy,
+                             Y ? Y + static_cast<long>(c1) * ldy : nullptr, ldy, &g, s);
+  if (e != hipSuccess) return e;
+  const int tx_next = (c2 - c1) / EMU_TILE;  // the next panel's column tiles
+  EmuGemmArgs u = g;
+  u.ntx = tx_next;
+  e = emu_run(u, K, s);
+  if (e != hipSuccess) return e;
+  e = stream_wait(s2, s, ss->ev[2]);
+  if (e != hipSuccess) return e;
+  EmuGemmArgs v = g;
+  v.tx0 = tx_next;
+  v.ntx = g.nt - tx_next;
+  if (v.ntx <= 0) return hipEventRecord(ss->ev[3], s2);
+  // row chunks as in the FP64 path (the tuned count is in 128 x 128 tiles)
+  int rows = M;
+  const int chunk_tiles = gemm_tuning().side_chunk_tiles;
+  if (chunk_tiles > 0 && s2 != s) {
+    const int tx = (v.ntx * EMU_TILE + GEMM_TILE - 1) / GEMM_TILE;
+    rows = std::max(1, chunk_tiles / std::max(1, tx)) * GEMM_TILE;
+  }
+  bool marked = false;
+  for (int r0 = 0; r0 < M; r0 += rows) {
+    EmuGemmArgs vc = v;
+    vc.ty0 = r0 / EMU_TILE;
+    vc.nty = (std::min(rows, M - r0) + EMU_TILE - 1) / EMU_TILE;
+    e = emu_run(vc, K, s2);
+    if (e != hipSuccess) return e;
+    if (!marked && r0 + rows >= std::min(NB2, M)) {
+      e = hipEventRecord(ss->ev[3], s2);
+      if (e != hipSuccess) return e;
+      marked = true;
+    }
+  }
+  return hipSuccess;
+}
+
 // LDU factorization of K in place; Y (if given, n+1 columns) is eliminated too.
 //
 // Look-ahead: the update of panel p's trailing matrix is split.  Its first
@@ -60,7 +164,8 @@ inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
 // for that part (event), and the call joins s2 back into s at the end.  The
 // arithmetic and its order per element are the same as without the split.
 template <class T>
-hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc, hipStream_t s) {
+hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc, hipStream_t s,
+                          const EmuWork* ew = nullptr) {
   const long ldk = f.ldk;
   T* kf = f.kf;
   SideStream* ss = nullptr;
@@ -119,7 +224,12 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
     }
     // (3) everything below and right of the panel: K = panel-width GEMMs,
     // the next panel's columns on s, the rest on s2
-    if (c1 < f.np) {
+    if (c1 < f.np && ew) {
+      if constexpr (std::is_same<T, double>::value) {
+        e = factor_update_emu(*ew, f, c0, c1, c2, Y, ldy, wy, s, s2, ss);
+        if (e != hipSuccess) return e;
+      }
+    } else if (c1 < f.np) {
       GemmArgs<T> u = update_args<T>(kf + static_cast<long>(c1) * ldk + c0, ldk, f.np - c1, c1 - c0);
       gemm_add_segment<T>(u, kf + static_cast<long>(c0) * ldk + c1, ldk, kf + static_cast<long>(c1) * ldk + c1,
                           ldk, c2 - c1);
@@ -252,7 +362,8 @@ struct PanelSweep {
 // the last, Y_p <- W_p Y_p, then the rows above take the panel's contribution
 // in one K = panel-width product.
 template <class T>
-hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s) {
+hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s,
+                      const EmuWork* ew = nullptr) {
   const long ldk = f.ldk;
   PanelSweep<T> ps;
   hipError_t e = ps.init(scr, lds, s);
@@ -265,7 +376,16 @@ hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
-    if (c0 > 0) {
+    if (c0 > 0 && ew) {
+      if constexpr (std::is_same<T, double>::value) {
+        EmuGemmArgs g;
+        e = emu_product(*ew, emu_operand(f.kf + c0, ldk, 1, c0, c1 - c0), true,
+                        emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, 0, nullptr, 0, &g, s);
+        if (e != hipSuccess) return e;
+        e = emu_run(g, c1 - c0, s);
+        if (e != hipSuccess) return e;
+      }
+    } else if (c0 > 0) {
       GemmArgs<T> u = update_args<T>(f.kf + c0, ldk, c0, c1 - c0);
       gemm_add_segment<T>(u, ps.cur, lds, Y, ldy, wy);
       RAD_GEMM(u, false);
@@ -277,7 +397,8 @@ hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds
 // Y <- K^{-T} Y in place:  U^T Z = Y  then  L^T Lambda = Z, panel by panel
 // with the transposed panel inverses.
 template <class T>
-hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s) {
+hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds, hipStream_t s,
+                            const EmuWork* ew = nullptr) {
   const long ldk = f.ldk;
   PanelSweep<T> ps;
   hipError_t e = ps.init(scr, lds, s);
@@ -290,7 +411,17 @@ hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, lo
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
-    if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
+    if (c1 < f.np && ew) {
+      if constexpr (std::is_same<T, double>::value) {
+        EmuGemmArgs g;
+        e = emu_product(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk + c1, 1, ldk, f.np - c1, c1 - c0),
+                        false, emu_operand(ps.cur, 1, lds, wy, c1 - c0), f.np - c1, wy,
+                        Y + static_cast<long>(c1) * ldy, ldy, 0, nullptr, 0, &g, s);
+        if (e != hipSuccess) return e;
+        e = emu_run(g, c1 - c0, s);
+        if (e != hipSuccess) return e;
+      }
+    } else if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk + c1, ldk, f.np - c1, c1 - c0);
       gemm_add_segment<T>(u, ps.cur, lds, Y + static_cast<long>(c1) * ldy, ldy, wy);
       RAD_GEMM(u, true);
@@ -308,7 +439,16 @@ hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, lo
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
-    if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
+    if (c0 > 0 && ew) {
+      if constexpr (std::is_same<T, double>::value) {
+        EmuGemmArgs g;
+        e = emu_product(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk, 1, ldk, c0, c1 - c0), false,
+                        emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, 0, nullptr, 0, &g, s);
+        if (e != hipSuccess) return e;
+        e = emu_run(g, c1 - c0, s);
+        if (e != hipSuccess) return e;
+      }
+    } else if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
       GemmArgs<T> u = update_args<T>(f.kf + static_cast<long>(c0) * ldk, ldk, c0, c1 - c0);
       gemm_add_segment<T>(u, ps.cur, lds, Y, ldy, wy);
       RAD_GEMM(u, true);
@@ -327,6 +467,7 @@ struct GebWork {
   double* p;    // FP64 P = F_sq diag(rho) (np x ldp), refinement only
   long ldp;
   double* part; // grad_eps partial sums (adjoint)
+  EmuWork emu;  // digit buffers (RAD_PREC_FP64_I8)
   void* scr;    // (T) two panels of right-hand sides (2 NB2 x ldy), shared with
                 // the panel-inverse products (tri_tmp_elems, ld ldt)
   long ldt;
@@ -339,9 +480,17 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
   GebWork w{};
   const int64_t np = ceil_div(n, NB) * NB;
   w.sc = cv.take<Scalars>(1);
-  if (prec == RAD_PREC_FP64) {
+  if (prec == RAD_PREC_FP64 || prec == RAD_PREC_FP64_I8) {
     w.ldy = rhs_ld(n, pad_elems<double>());
     w.y = cv.take<double>(static_cast<size_t>(np) * w.ldy);
+    if (prec == RAD_PREC_FP64_I8) {
+      // op(A) has at most np rows, B^T at most np + n + 1 (U block and RHS)
+      const long rb = np + n + 1;
+      w.emu.da = cv.take<int8_t>(emu_digit_bytes(np, NB2));
+      w.emu.db = cv.take<int8_t>(emu_digit_bytes(rb, NB2));
+      w.emu.sa = cv.take<double>(emu_scale_count(np, NB2));
+      w.emu.sb = cv.take<double>(emu_scale_count(rb, NB2));
+    }
   } else {
     w.ldy = rhs_ld(n, pad_elems<float>());
     w.y = cv.take<float>(static_cast<size_t>(np) * w.ldy);
@@ -353,7 +502,7 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
   }
   if (adjoint) w.part = cv.take<double>(static_cast<size_t>(ceil_div(n, GE_ROWS) * n));
   {
-    const size_t es = prec == RAD_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t es = prec == RAD_PREC_FP32_IR ? sizeof(float) : sizeof(double);
     const long pad = static_cast<long>(128 / es);
     const int P2 = static_cast<int>(ceil_div(np, NB2));
     w.ldt = tri_ldt(pad);
@@ -367,8 +516,10 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
 }
 
 size_t factor_bytes(int64_t n, int32_t prec) {
-  return prec == RAD_PREC_FP64 ? factor_layout<double>(n).bytes : factor_layout<float>(n).bytes;
+  return prec == RAD_PREC_FP32_IR ? factor_layout<float>(n).bytes : factor_layout<double>(n).bytes;
 }
+
+bool known_precision(int32_t p) { return p == RAD_PREC_FP64 || p == RAD_PREC_FP32_IR || p == RAD_PREC_FP64_I8; }
 
 int read_scalars(Scalars* dev, Scalars* host, hipStream_t s) {
   RAD_HIP_CHECK(hipMemcpyAsync(host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, s));
@@ -388,12 +539,12 @@ void zero(T* p, long count, hipStream_t s) {
 using namespace rad;
 
 extern "C" size_t rad_gebhart_factor_bytes(int64_t n, int32_t precision) {
-  if (n < 1 || (precision != RAD_PREC_FP64 && precision != RAD_PREC_FP32_IR)) return 0;
+  if (n < 1 || !known_precision(precision)) return 0;
   return factor_bytes(n, precision);
 }
 
 extern "C" size_t rad_gebhart_workspace_bytes(int64_t n, int32_t precision) {
-  if (n < 1 || (precision != RAD_PREC_FP64 && precision != RAD_PREC_FP32_IR)) return 0;
+  if (n < 1 || !known_precision(precision)) return 0;
   return geb_work(nullptr, 0, n, precision, false).bytes;
 }
 
@@ -405,8 +556,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
   RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_gebhart_ref: n out of range");
   RAD_REQUIRE(ldf >= n + 1 && ldb >= n + 1, RAD_EINVAL, "rad_gebhart_ref: ldf or ldb < n+1");
   RAD_REQUIRE(F && eps && rho && B && factors, RAD_EINVAL, "rad_gebhart_ref: NULL pointer");
-  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP32_IR, RAD_EINVAL,
-              "rad_gebhart_ref: unknown precision");
+  RAD_REQUIRE(known_precision(precision), RAD_EINVAL, "rad_gebhart_ref: unknown precision");
   RAD_REQUIRE(ir_max >= 0 && ir_tol >= 0.0, RAD_EINVAL, "rad_gebhart_ref: ir_max < 0 or ir_tol < 0");
   RAD_REQUIRE(fbytes >= factor_bytes(n, precision) && reinterpret_cast<uintptr_t>(factors) % 256 == 0,
               RAD_EWORKSPACE, "rad_gebhart_ref: factor buffer too small or not 256-byte aligned");
@@ -420,14 +570,15 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
                      eps, rho, ni, w.sc);
   int ir_steps = 0;
   Scalars h{};
-  if (precision == RAD_PREC_FP64) {
+  if (precision != RAD_PREC_FP32_IR) {
+    const EmuWork* ew = precision == RAD_PREC_FP64_I8 ? &w.emu : nullptr;
     Fact<double> f = make_fact<double>(factors, factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
     hipLaunchKernelGGL(geb_form<double>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
                        rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
-    RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s));
+    RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s, ew));
     RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
-    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s));
+    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s, ew));
     hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
                        static_cast<long>(ldb));
   } else {
@@ -467,7 +618,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     }
   }
   RAD_HIP_CHECK(hipGetLastError());
-  if (!stats && precision == RAD_PREC_FP64) return RAD_OK;
+  if (!stats && precision != RAD_PREC_FP32_IR) return RAD_OK;
   int rc = read_scalars(w.sc, &h, s);
   if (rc != RAD_OK) return rc;
   if (stats) {
@@ -476,7 +627,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     stats->device_status = h.status;
     stats->ir_correction = h.max_d;
     stats->ir_residual = h.max_r;
-    stats->converged = (precision == RAD_PREC_FP64) || (ir_steps > 0 && h.max_d <= ir_tol);
+    stats->converged = (precision != RAD_PREC_FP32_IR) || (ir_steps > 0 && h.max_d <= ir_tol);
   }
   if (h.status < 0) {
     set_error(h.status == RAD_ESINGULAR ? "rad_gebhart_ref: singular diagonal block of K"
@@ -526,7 +677,7 @@ extern "C" int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const 
 }
 
 extern "C" size_t rad_adjoint_workspace_bytes(int64_t n, int32_t precision) {
-  if (n < 1 || (precision != RAD_PREC_FP64 && precision != RAD_PREC_FP32_IR)) return 0;
+  if (n < 1 || !known_precision(precision)) return 0;
   return geb_work(nullptr, 0, n, precision, true).bytes;
 }
 
@@ -542,8 +693,7 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
               "rad_gebhart_ref_adjoint: leading dimension < n+1");
   RAD_REQUIRE(factors && F && rho && B && G && grad_eps && grad_rho, RAD_EINVAL,
               "rad_gebhart_ref_adjoint: NULL pointer");
-  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP32_IR, RAD_EINVAL,
-              "rad_gebhart_ref_adjoint: unknown precision");
+  RAD_REQUIRE(known_precision(precision), RAD_EINVAL, "rad_gebhart_ref_adjoint: unknown precision");
   RAD_REQUIRE(ir_max >= 0 && ir_tol >= 0.0, RAD_EINVAL, "rad_gebhart_ref_adjoint: bad ir_max / ir_tol");
   RAD_REQUIRE(fbytes >= factor_bytes(n, precision), RAD_EWORKSPACE,
               "rad_gebhart_ref_adjoint: factor buffer smaller than the factorization of n");
@@ -557,11 +707,12 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
   long ldlam = 0;
   int ir_steps = 0;
   Scalars h{};
-  if (precision == RAD_PREC_FP64) {
+  if (precision != RAD_PREC_FP32_IR) {
+    const EmuWork* ew = precision == RAD_PREC_FP64_I8 ? &w.emu : nullptr;
     Fact<double> f = make_fact<double>(const_cast<void*>(factors), factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
     hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
-    RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s));
+    RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s, ew));
     lam = Y;
     ldlam = w.ldy;
   } else {
@@ -615,7 +766,7 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
   stats->device_status = h.status;
   stats->ir_correction = h.max_d;
   stats->ir_residual = h.max_r;
-  stats->converged = (precision == RAD_PREC_FP64) || (ir_steps > 0 && h.max_d <= ir_tol);
+  stats->converged = (precision != RAD_PREC_FP32_IR) || (ir_steps > 0 && h.max_d <= ir_tol);
   if (precision == RAD_PREC_FP32_IR && ir_max > 0 && !(h.max_d <= ir_tol)) return RAD_WNOTCONVERGED;
   return RAD_OK;
 }

@@ -61,3 +61,17 @@ def test_tuning_roundtrip_and_validation():
         assert _lib.tuning()["small_tile_below_f64"] == 300  # unchanged by a rejected call
     finally:
         _lib.apply_tuning(saved)
+
+
+def test_precision_size_queries():
+    lib = _lib.lib()
+    n = 4000
+    f64 = lib.rad_gebhart_factor_bytes(n, _lib.RAD_PREC_FP64)
+    # the int8-emulated mode keeps FP64 factors and adds the digit buffers
+    assert lib.rad_gebhart_factor_bytes(n, _lib.RAD_PREC_FP64_I8) == f64
+    w64 = lib.rad_gebhart_workspace_bytes(n, _lib.RAD_PREC_FP64)
+    assert lib.rad_gebhart_workspace_bytes(n, _lib.RAD_PREC_FP64_I8) > w64 + 7 * 4096 * 1024
+    assert lib.rad_adjoint_workspace_bytes(n, _lib.RAD_PREC_FP64_I8) > lib.rad_adjoint_workspace_bytes(
+        n, _lib.RAD_PREC_FP64)
+    for q in (lib.rad_gebhart_factor_bytes, lib.rad_gebhart_workspace_bytes, lib.rad_adjoint_workspace_bytes):
+        assert q(n, 3) == 0 and q(0, _lib.RAD_PREC_FP64_I8) == 0

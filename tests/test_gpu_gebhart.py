@@ -107,7 +107,7 @@ def test_invalid_optical_properties():
     assert e.value.code == -2
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "fp64_i8"])
 def test_full_size_open_cube_n5120(precision):
     """The 5120-face open cube: enforced on the GPU, then solved; element-wise vs the oracle."""
     need_gpu()
@@ -122,12 +122,13 @@ def test_full_size_open_cube_n5120(precision):
     ref = oracle.gebhart_ref(f, eps, rho)
     err = np.abs(host(bd) - ref).max()
     print(f"[gebhart] n=5120 {precision} max|dB|={err:.3e} stats={st}", flush=True)
-    assert err <= (TOL64 if precision == "fp64" else TOL_IR)
+    assert err <= {"fp64": TOL64, "fp32_ir": TOL_IR, "fp64_i8": TOL_IR}[precision]
 
 
 def test_full_size_open_box_n16384_sampled_columns():
     """The 16384-face open box (1 x 1 x 0.75 m, 1e4 rays), enforced on the GPU and
-    solved in FP64 and in FP32 + one FP64 refinement step, each within 1e-10 of the
+    solved in FP64, in FP32 + one FP64 refinement step and with int8-emulated
+    products, each within 1e-10 of the
     oracle on 48 seeded columns (the space column included); closure and reciprocity
     of the whole REF matrix (eq. 4.3-4.4) checked on the GPU."""
     need_gpu()
@@ -149,7 +150,7 @@ def test_full_size_open_box_n16384_sampled_columns():
     print("[gebhart] n=16384: oracle LU", flush=True)
     ref = sla.lu_solve(sla.lu_factor(k), e[:, cols])
     del k, e, f
-    for precision, ir_tol, ir_max in (("fp64", 0.0, 0), ("fp32_ir", 1.0, 1)):
+    for precision, ir_tol, ir_max in (("fp64", 0.0, 0), ("fp32_ir", 1.0, 1), ("fp64_i8", 0.0, 0)):
         bd, _, st = rad.gebhart_ref(fd, dev(eps), dev(rho), precision=precision, ir_tol=ir_tol, ir_max=ir_max)
         chk = host(rad.ref_check(bd, dev(eps), area))
         got = host(bd[:, torch.as_tensor(cols, device="cuda")])
@@ -158,9 +159,10 @@ def test_full_size_open_box_n16384_sampled_columns():
         print(f"[gebhart] n=16384 {precision} sampled max|dB|={err:.3e} closure={chk[0]:.2e} "
               f"reciprocity={chk[1] / scale:.2e} (relative) stats={st}", flush=True)
         assert err <= TOL_IR
-        # FP64: rounding level; FP32 + one refinement step: its elementwise
-        # error (~1e-12) summed along a row stays below the 1e-10 target
-        lim = 1e-12 if precision == "fp64" else 1e-10
+        # FP64: rounding level; FP32 + one refinement step and the int8
+        # digit products: their elementwise error (~1e-12) summed along a
+        # row stays below the 1e-10 target
+        lim = {"fp64": 1e-12, "fp32_ir": 1e-10, "fp64_i8": 1e-10}[precision]
         assert chk[0] < lim and chk[1] < 10 * lim * scale
         del bd
         torch.cuda.empty_cache()
@@ -182,13 +184,13 @@ def test_tuning_knobs_leave_results_bitwise_unchanged():
         for tile, look, chunk in ((0, 1, 0), (4096, 1, 0), (1 << 30, 0, 0), (256, 0, 0), (4096, 1, 512), (0, 1, 100)):
             L.apply_tuning({"small_tile_below_f64": tile, "small_tile_below_f32": tile, "lookahead": look,
                             "side_chunk_tiles": chunk})
-            for prec in ("fp64", "fp32_ir"):
+            for prec in ("fp64", "fp32_ir", "fp64_i8"):
                 b, fac, _ = rad.gebhart_ref(fd, eps, rho, precision=prec, ir_tol=1e-13, ir_max=3)
                 ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, fd, rho, b, g)
                 outs.append((tile, look, prec, b.clone(), ge.clone(), gr.clone()))
     finally:
         L.apply_tuning(saved)
-    for prec in ("fp64", "fp32_ir"):
+    for prec in ("fp64", "fp32_ir", "fp64_i8"):
         ref = [o for o in outs if o[2] == prec]
         for o in ref[1:]:
             assert torch.equal(o[3], ref[0][3]) and torch.equal(o[4], ref[0][4]) and torch.equal(o[5], ref[0][5]), o[:3]

@@ -1,0 +1,85 @@
+"""GPU parity of RAD_PREC_FP64_I8 (FP64 solves whose panel-width products are
+exact int8 digit products, FP64 accumulation) against the FP64 oracle.
+
+The emulated products only run where a panel has rows or columns beyond it,
+so the cases have n > 1024 (two to four 1024-wide panels, ragged tails).
+Each dropped digit pair and operand tail is below 2^-49 of the row and
+column maxima per unit of K; summed over the panel updates and both
+substitutions that leaves about 1e-12 on B at these sizes (FP64: 3e-15).
+The bound used here, 1e-11 absolute on B and relative on the adjoint, is ten
+times inside the 1e-10 target; a row sum of n + 1 such errors (closure) is
+held to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import workloads as W
+from tests.gpu_util import dev, host, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.mark.parametrize("n", [1100, 2300, 3000])
+def test_solve_matches_oracle(n):
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(n, seed=n)
+    eps, rho = inst.eps[0], inst.rho[0]
+    print(f"[i8x] solve n={inst.n}", flush=True)
+    bd, _, st = rad.gebhart_ref(dev(inst.f_noisy), dev(eps), dev(rho), precision="fp64_i8")
+    ref = oracle.gebhart_ref(inst.f_noisy, eps, rho)
+    err = np.abs(host(bd) - ref).max()
+    print(f"[i8x] n={inst.n} max|dB|={err:.3e} stats={st}", flush=True)
+    assert err <= TOL
+
+
+def test_rho_zero_gives_e_exactly():
+    """rho = 0: L = I, so every emulated update adds exact zeros."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(2100, seed=5)
+    eps = inst.eps[0]
+    bd, _, _ = rad.gebhart_ref(dev(inst.f_noisy), dev(eps), dev(np.zeros(inst.n)), precision="fp64_i8")
+    _, e = oracle.form_k_e(inst.f_noisy, eps, np.zeros(inst.n))
+    assert np.abs(host(bd) - e).max() == 0.0
+
+
+def test_adjoint_matches_oracle():
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(2300, seed=31)
+    n = inst.n
+    f, eps, rho = inst.f_noisy, inst.eps[0], inst.rho[0].copy()
+    rho[7] = 1e-4  # the direct small-rho form
+    g = np.random.default_rng(2).uniform(-1, 1, (n, n + 1))
+    print(f"[i8x] adjoint n={n}", flush=True)
+    fd, rd = dev(f), dev(rho)
+    bd, fac, _ = rad.gebhart_ref(fd, dev(eps), rd, precision="fp64_i8")
+    ge, gr, lam, _ = rad.gebhart_ref_adjoint(fac, fd, rd, bd, dev(g), want_lambda=True)
+    b = oracle.gebhart_ref(f, eps, rho)
+    rge, rgr, rlam = oracle.gebhart_ref_adjoint(f, eps, rho, b, g)
+
+    def rel(a, r):
+        return np.abs(a - r).max() / np.abs(r).max()
+    print(f"[i8x] adjoint rel err lambda={rel(host(lam), rlam):.2e} eps={rel(host(ge), rge):.2e} "
+          f"rho={rel(host(gr), rgr):.2e}", flush=True)
+    assert rel(host(lam), rlam) <= TOL and rel(host(ge), rge) <= TOL and rel(host(gr), rgr) <= TOL
+
+
+def test_ref_checks_and_fp64_agreement():
+    """On an enforced F the emulated B keeps closure and reciprocity at
+    rounding level and agrees with the FP64 path's B."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(2200, seed=12)
+    fd, area = dev(inst.f_noisy), dev(inst.area)
+    rad.enforce_vf_(fd, area, dev(inst.n_rays), tol=1e-14, max_iter=200)
+    eps, rho = dev(inst.eps[0]), dev(inst.rho[0])
+    b64, _, _ = rad.gebhart_ref(fd, eps, rho, precision="fp64")
+    b8, _, _ = rad.gebhart_ref(fd, eps, rho, precision="fp64_i8")
+    chk = host(rad.ref_check(b8, eps, area))
+    d = torch.max(torch.abs(b8 - b64)).item()
+    print(f"[i8x] closure={chk[0]:.2e} reciprocity={chk[1]:.2e} max|B_i8 - B_64|={d:.2e}", flush=True)
+    assert d <= TOL and chk[0] < 1e-10 and chk[1] < 1e-13

@@ -3,7 +3,7 @@
 Two enforce -> solve -> adjoint pipelines issued on two streams at once
 (their own buffers, the binding's per-stream workspaces, the library's shared
 side stream for the look-ahead) must give bit for bit what each gives alone,
-in FP64 and in FP32 with refinement.
+in FP64, in FP32 with refinement and with int8-emulated products.
 """
 import numpy as np
 import pytest
@@ -22,7 +22,7 @@ def _pipeline(rad, f0, area, nrays, eps, rho, g, precision):
     return f, b, ge, gr
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "fp64_i8"])
 def test_two_streams_match_sequential(precision):
     need_gpu()
     import paper_2511_04277_amd as rad
