@@ -48,14 +48,20 @@ def solve_flops(n: int) -> float:
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * (n + 1)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_lds_f64_open_box_n8192_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2511_04277_amd", "csrc", "gemm.h")]
+# counter summaries per dominant kernel: (file, sources whose hash it records)
+_CSRC = os.path.join(ROOT, "paper_2511_04277_amd", "csrc")
+TRAFFIC = {
+    "gemm_lds<double, false>": (os.path.join(ROOT, "profiles", "gemm_lds_f64_open_box_n8192_traffic.txt"),
+                                [os.path.join(_CSRC, "gemm.h")]),
+    "emu_gemm<7>": (os.path.join(ROOT, "profiles", "emu_gemm_open_box_n8192_traffic.txt"),
+                    [os.path.join(_CSRC, "emu_kernels.h")]),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources) -> str:
     import hashlib
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
+    for path in sources:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -69,15 +75,18 @@ def measured_traffic(kname: str, prec: str):
     the hash of the kernel source they were taken on; a changed kernel gives
     None (counters are stale).
     """
-    if prec != "fp64" or not os.path.exists(TRAFFIC_FILE):
+    if kname not in TRAFFIC:
+        return None
+    path, sources = TRAFFIC[kname]
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_hash() or vals.get("kernel") != kname:
+    if vals.get("kernel_source_sha256") != kernel_source_hash(sources) or vals.get("kernel") != kname:
         return None
     return float(vals["hbm_bytes_per_launch"])
 

@@ -94,7 +94,8 @@ inline hipError_t emu_run(const EmuGemmArgs& g, int K, hipStream_t s) {
   const double rows = std::max(0, std::min(g.M, (g.ty0 + g.nty) * EMU_TILE) - g.ty0 * EMU_TILE);
   const double cols = std::max(0, std::min(g.N[0] + (g.nseg > 1 ? g.N[1] : 0), (g.tx0 + g.ntx) * EMU_TILE) -
                                       g.tx0 * EMU_TILE);
-  ProfScope prof(s, RAD_PROF_GEMM_I8X, 2.0 * rows * cols * K, 8.0 * rows * cols * 2.0);
+  // algorithmic bytes: C read and written, the digits of both operands read once
+  ProfScope prof(s, RAD_PROF_GEMM_I8X, 2.0 * rows * cols * K, 16.0 * rows * cols + EMU_S * (rows + cols) * K);
   return emu_launch(g, s);
 }
 
