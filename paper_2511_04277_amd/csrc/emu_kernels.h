@@ -2,24 +2,25 @@
 //
 //   C[seg] += alpha * A * B,   A: M x K,  B: K x N,  C FP64
 //
-// Error-free splitting (Ozaki's scheme): each k block of 64 of every row r
-// of an operand (a row of A, a column of B) is scaled by the power of two
-// sigma_r,kb > max_{k in kb} |X_rk| and written as S signed 7-bit digits,
+// Error-free splitting (Ozaki's scheme): every row r of an operand (a row of
+// A, a column of B) is scaled by the power of two sigma_r = 2^e_r >
+// max_k |X_rk| and written as S signed 7-bit digits,
 //
-//   X_rk = sigma_r,kb * sum_{s<S} d_s(r,k) 2^{-7(s+1)} + t_rk,  |d_s| <= 127,
-//   |t_rk| < sigma_r,kb 2^{-7S},
+//   X_rk = sigma_r * sum_{s<S} d_s(r,k) 2^{-7(s+1)} + t_rk,   |d_s| <= 127,
+//   |t_rk| < sigma_r 2^{-7S},
 //
 // each step (scale by 128, truncate, subtract) exact in FP64.  Products of
-// digit matrices D^A_s D^B_t over one k block are exact in int32
-// (v_mfma_i32_16x16x64_i8); the pairs with s + t >= S are dropped, the kept
-// pairs are summed in int32 by class d = s + t, weighted by 2^{-7(d+2)} in
-// FP64 and added to FP64 accumulators with the block's sigma^A_i sigma^B_j.
-// Per element and k block the result differs from the exact product by less
-// than
-//   (S + 3) 64 sigma^A_i,kb sigma^B_j,kb 2^{-7S}
-// (the two tails and the dropped pairs) plus FP64 accumulation rounding; with
-// S = 7 that is 2^-49 per unit of 64 sigma^A sigma^B as a worst case, and in
-// practice (errors of random sign) a few hundred FP64 ulps of the product.
+// digit matrices D^A_s D^B_t are exact in int32 (v_mfma_i32_16x16x64_i8);
+// the pairs with s + t >= S are dropped, and the kept pairs accumulate in
+// int32 per class d = s + t over the whole K (|sum| <= S K 127^2 < 2^31 for
+// K <= EMU_MAX_K), so the FP64 work is one fold per output element:
+// sum_d acc_d 2^{-7(d+2)}, times sigma^A_i sigma^B_j.  Per element the result
+// differs from the exact product by less than
+//   (S + 3) K sigma^A_i sigma^B_j 2^{-7S}
+// (the two tails and the dropped pairs) plus the fold's FP64 rounding; with
+// S = 7 that is 2^-49 per unit of K sigma^A sigma^B as a worst case, and in
+// practice (errors of random sign) about 2^-49 sqrt(K) of the row and column
+// maxima.
 //
 // Digit layout (written by emu_split, read by emu_gemm): operand rows padded
 // to a multiple of 64 (T tiles) and k to 64 nkb.  The 64 rows x S slices x
@@ -42,6 +43,8 @@ constexpr int EMU_S = 7;          // digits per operand element
 constexpr int EMU_TILE = 64;      // C tile of one workgroup (64 x 64)
 constexpr int EMU_KB = 64;        // k per stage (one MFMA 16 x 16 x 64)
 constexpr int EMU_THREADS = 256;  // four waves, 32 x 32 of C each
+constexpr int EMU_MAX_K = 16384;  // S K 127^2 < 2^31 for S = 7
+constexpr int EMU_EXP_NONE = -2000;  // scale exponent of an all-zero row
 
 typedef int emu_v4i __attribute__((ext_vector_type(4)));
 
@@ -73,14 +76,50 @@ __device__ __forceinline__ double emu_load(const EmuOperand& op, int r, int k) {
   return op.X[q][rr * op.sr[q] + static_cast<long>(k) * op.sk[q]];
 }
 
-// Scale and digits of one 64-row x 64-k block per workgroup.  The block's
-// doubles are read with 512-byte contiguous loads in whichever orientation the
-// operand has and transposed through LDS; thread t takes 16 consecutive k of
-// row t / 4 (chunk c = t % 4), the four threads of a row agree on the row's
-// maximum, the one with chunk 0 writes sigma, and a wave's stores of one
-// slice are one contiguous 1 KB piece of the block.
+// Scale exponents e_r (max_k |X_rk| < 2^e_r; EMU_EXP_NONE for a zero row).
+// k-contiguous rows: one wave per row.
+static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int Rp, int* __restrict__ ex) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (r >= Rp) return;
+  double m = 0.0;
+  for (int k = l; k < op.K; k += 64) m = fmax(m, fabs(emu_load(op, r, k)));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  int e = 0;
+  if (m > 0.0) frexp(m, &e);  // m = f 2^e, f in [0.5, 1): m < 2^e
+  if (l == 0) ex[r] = m > 0.0 ? e : EMU_EXP_NONE;
+}
+
+// Rows contiguous in memory: a workgroup takes 256 rows x 64 k (each thread
+// one row, every load instruction 512 contiguous bytes) and merges its
+// exponents by atomic maxima; ex must hold EMU_EXP_NONE beforehand.
+static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int Rp, int* __restrict__ ex) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int k0 = blockIdx.y * EMU_KB;
+  if (r >= Rp) return;
+  double m = 0.0;
+#pragma unroll 8
+  for (int k = k0; k < k0 + EMU_KB; ++k) m = fmax(m, fabs(emu_load(op, r, k)));
+  if (m > 0.0) {
+    int e = 0;
+    frexp(m, &e);
+    atomicMax(&ex[r], e);
+  }
+}
+
+static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Digits of one 64-row x 64-k block per workgroup.  The block's doubles are
+// read with 512-byte contiguous loads in whichever orientation the operand has
+// and transposed through LDS; thread t forms the S digits of 16 consecutive k
+// of row t / 4 (chunk c = t % 4), and a wave's stores of one slice are one
+// contiguous 1 KB piece of the block.
 template <int S, bool KC>
-__global__ __launch_bounds__(256) void emu_split(EmuOperand op, double* __restrict__ sig, int8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void emu_split(EmuOperand op, const int* __restrict__ ex, int8_t* __restrict__ out) {
   __shared__ double tile[EMU_TILE][EMU_KB + 1];
   const int rt = blockIdx.x, kb = blockIdx.y;
   const int t = threadIdx.x;
@@ -94,26 +133,15 @@ __global__ __launch_bounds__(256) void emu_split(EmuOperand op, double* __restri
   }
   __syncthreads();
   const int row = t >> 2, c = t & 3;
-  double x[16], m = 0.0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    x[i] = tile[row][c * 16 + i];
-    m = fmax(m, fabs(x[i]));
-  }
-  m = fmax(m, __shfl_xor(m, 1));
-  m = fmax(m, __shfl_xor(m, 2));
-  int ex = 0;
-  if (m > 0.0) frexp(m, &ex);  // m = f 2^ex, f in [0.5, 1): m < 2^ex
-  const double sg = m > 0.0 ? ldexp(1.0, ex) : 1.0;
-  if (c == 0) sig[static_cast<long>(kb) * gridDim.x * EMU_TILE + r0 + row] = sg;
-  const double inv = 1.0 / sg;  // a power of two: exact
+  const int e = ex[r0 + row];
+  const int es = e == EMU_EXP_NONE ? 0 : e;
   union {
     emu_v4i v;
     int8_t b[16];
   } dg[S];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    double a = x[i] * inv;
+    double a = ldexp(tile[row][c * 16 + i], -es);  // exact
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       a *= 128.0;
@@ -131,9 +159,9 @@ __global__ __launch_bounds__(256) void emu_split(EmuOperand op, double* __restri
 
 struct EmuGemmArgs {
   const int8_t* A;   // digits of A: mt 64-row tiles per k block
-  const double* sa;  // scales of A per k block and row ([kb][64 mt])
+  const int* xa;     // scale exponents of the rows of A
   const int8_t* B;   // digits of B^T (rows = columns of C): nt tiles per k block
-  const double* sb;  // scales of B per k block and column ([kb][64 nt])
+  const int* xb;     // scale exponents of the columns of B
   int mt, nt, nkb;
   int ty0, nty;      // the launch covers A tiles [ty0, ty0 + nty) ...
   int tx0, ntx;      // ... times B tiles [tx0, tx0 + ntx)
@@ -145,15 +173,13 @@ struct EmuGemmArgs {
   long ldc[2];
 };
 
-// One 64 x 64 tile of C per workgroup, two workgroups per CU (64 KB of LDS
+// One 64 x 64 tile of C per workgroup, two workgroups per CU (56 KB of LDS
 // each, at most 256 registers per lane).  Per k block: the block's digits
 // arrive in LDS by global-to-LDS copies, every wave reads all its fragments
 // (S slices x 2 row blocks of A, S x 2 column blocks of B) into registers, the
-// LDS is released and the next block's copies start, and the MFMAs run from
-// registers meanwhile.  The digit pairs are taken class by class (d = s + t)
-// into one of two int32 accumulator sets, and each finished class is added to
-// the FP64 accumulators with its weight 2^{-7(d+2)} while the next class's
-// MFMAs run.
+// LDS is released and the next block's copies start, and the 28 digit-pair
+// MFMAs run from registers meanwhile into S int32 class accumulators that
+// persist over the whole K.
 template <int S>
 __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
   constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
@@ -166,7 +192,7 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const emu_v4i* ga = reinterpret_cast<const emu_v4i*>(g.A) + static_cast<long>(by) * CH;
   const emu_v4i* gb = reinterpret_cast<const emu_v4i*>(g.B) + static_cast<long>(bx) * CH;
-  const long stride_a = static_cast<long>(g.mt) * CH;  // chunks per k block
+  const long stride_a = static_cast<long>(g.mt) * CH;
   const long stride_b = static_cast<long>(g.nt) * CH;
   // copies of one k block: wave w moves 1 KB pieces w, w + 4, ... of A then B
   auto stage = [&](int kb) {
@@ -179,13 +205,13 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
     }
   };
   const int fr = l & 15, fc = l >> 4;
-  double acc[2][2][4];
+  emu_v4i ci[S][2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int d = 0; d < S; ++d)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+      for (int j = 0; j < 2; ++j) ci[d][i][j] = emu_v4i{0, 0, 0, 0};
   stage(0);
   for (int kb = 0; kb < g.nkb; ++kb) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
@@ -200,54 +226,19 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
       }
     __syncthreads();  // every wave holds its fragments: the LDS is free
     if (kb + 1 < g.nkb) stage(kb + 1);
-    // this block's scales of the lane's 8 rows and 2 columns
-    double sai[2][4], sbj[2];
+    // pair (s, u) into class s + u; consecutive MFMAs go to different classes
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      sbj[i] = g.sb[static_cast<long>(kb) * g.nt * EMU_TILE + bx * EMU_TILE + wc + 16 * i + fr];
+    for (int s = 0; s < S; ++s)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        sai[i][v] = g.sa[static_cast<long>(kb) * g.mt * EMU_TILE + by * EMU_TILE + wr + 16 * i + 4 * fc + v];
-    }
-    double y[2][2][4];
-    // class d (pairs s + t = d) goes to int32 set d % 2; a finished pair of
-    // classes (d - 1, d) is folded as 128 acc_{d-1} + acc_d (exact: per k
-    // block |acc_d| <= 8 * 64 * 127^2, so the fold stays below 2^30) and added
-    // to the FP64 accumulators with weight 2^{-7(d+2)}
-    emu_v4i ci[2][2][2];
-    const emu_v4i zero = {0, 0, 0, 0};
-    auto flush = [&](int d, bool pair) {
-      const double wgt = ldexp(1.0, -7 * (d + 2));
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int x = pair ? ci[0][i][j][v] * 128 + ci[1][i][j][v] : ci[d & 1][i][j][v];
-            y[i][j][v] = d == 1 ? static_cast<double>(x) * wgt : fma(static_cast<double>(x), wgt, y[i][j][v]);
-          }
-    };
-#pragma unroll
-    for (int d = 0; d < S; ++d) {
-#pragma unroll
-      for (int s = 0; s <= d; ++s)
+      for (int u = 0; u < S - s; ++u)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            ci[d & 1][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[s][i], bf[d - s][j], s == 0 ? zero : ci[d & 1][i][j], 0, 0, 0);
-      if (d & 1) flush(d, true);
-    }
-    if (S & 1) flush(S - 1, false);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[i][j][v] = fma(y[i][j][v], sai[i][v] * sbj[j], acc[i][j][v]);
+            ci[s + u][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[s][i], bf[u][j], ci[s + u][i][j], 0, 0, 0);
   }
-  // epilogue: lane l holds rows 4 (l / 16) + v, column l % 16 of each block
+  // epilogue: lane l holds rows 4 (l / 16) + v, column l % 16 of each block;
+  // one FP64 fold of the S class sums per element
   const int row0 = by * EMU_TILE + wr, col0 = bx * EMU_TILE + wc;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -258,6 +249,7 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
       cc = col - g.N[0];
     }
     if (cc >= g.N[seg] || seg >= g.nseg) continue;
+    const int eb = g.xb[col];
     double* Cc = g.C[seg] + cc;
     const long ldc = g.ldc[seg];
 #pragma unroll
@@ -266,8 +258,13 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + 16 * i + 4 * fc + v;
         if (row >= g.M) continue;
+        const int ea = g.xa[row];
+        if (ea == EMU_EXP_NONE || eb == EMU_EXP_NONE) continue;  // a zero row or column adds nothing
+        double x = 0.0;
+#pragma unroll
+        for (int d = S - 1; d >= 0; --d) x = fma(static_cast<double>(ci[d][i][j][v]), ldexp(1.0, -7 * (d + 2)), x);
         double* p = Cc + static_cast<long>(row) * ldc;
-        *p = fma(g.alpha, acc[i][j][v], *p);
+        *p = fma(g.alpha, ldexp(x, ea + eb), *p);
       }
   }
 }
@@ -279,23 +276,25 @@ inline size_t emu_digit_bytes(long R, long K) {
   return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB) * EMU_KB * EMU_S;
 }
 
-// Scales and digits of one operand (kc: k contiguous in memory, else rows).
-// sig holds one entry per k block and padded row.
-inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, double* sig, hipStream_t s) {
-  const int T = (op.R + EMU_TILE - 1) / EMU_TILE;
+// Scale exponents and digits of one operand (kc: k contiguous in memory,
+// else rows).  ex receives one exponent per padded row.
+inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, hipStream_t s) {
+  const int T = (op.R + EMU_TILE - 1) / EMU_TILE, Rp = T * EMU_TILE;
   const int nkb = (op.K + EMU_KB - 1) / EMU_KB;
   if (T == 0 || nkb == 0) return hipSuccess;
-  if (kc)
-    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(T, nkb), dim3(256), 0, s, op, sig, dig);
-  else
-    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(T, nkb), dim3(256), 0, s, op, sig, dig);
+  if (kc) {
+    hipLaunchKernelGGL(emu_rowexp_kc, dim3((Rp + 3) / 4), dim3(256), 0, s, op, Rp, ex);
+    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(T, nkb), dim3(256), 0, s, op, ex, dig);
+  } else {
+    hipLaunchKernelGGL(emu_fill_i32, dim3((Rp + 255) / 256), dim3(256), 0, s, ex, Rp, EMU_EXP_NONE);
+    hipLaunchKernelGGL(emu_rowexp_rc, dim3((Rp + 255) / 256, nkb), dim3(256), 0, s, op, Rp, ex);
+    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(T, nkb), dim3(256), 0, s, op, ex, dig);
+  }
   return hipGetLastError();
 }
 
-// Entries of the scale array of an operand with R rows and K columns.
-inline size_t emu_scale_count(long R, long K) {
-  return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB);
-}
+// Entries of the exponent array of an operand with R rows.
+inline size_t emu_scale_count(long R) { return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE; }
 
 inline hipError_t emu_launch(const EmuGemmArgs& g, hipStream_t s) {
   if (g.ntx <= 0 || g.nty <= 0 || g.nkb <= 0) return hipSuccess;

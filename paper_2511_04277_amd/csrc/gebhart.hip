@@ -67,8 +67,8 @@ inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
 struct EmuWork {
   int8_t* da;  // digits of op(A)
   int8_t* db;  // digits of B^T
-  double* sa;  // scales of op(A) per k block and row
-  double* sb;  // scales of B per k block and column
+  int* xa;     // scale exponents of the rows of op(A)
+  int* xb;     // scale exponents of the columns of B
 };
 
 // Scales and digits of both operands of C -= op(A) B; g receives the launch
@@ -76,16 +76,17 @@ struct EmuWork {
 // for j < N0 and C1[i ldc1 + j - N0] after.
 inline hipError_t emu_product(const EmuWork& e, const EmuOperand& oa, bool akc, const EmuOperand& ob, int M, int N0,
                               double* C0, long ldc0, int N1, double* C1, long ldc1, EmuGemmArgs* g, hipStream_t s) {
+  if (oa.K != ob.K || oa.K > EMU_MAX_K) return hipErrorInvalidValue;
   {
     ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0,
                    (8.0 + EMU_S) * (static_cast<double>(oa.R) + ob.R) * static_cast<double>(oa.K));
-    hipError_t err = emu_prepare(oa, akc, e.da, e.sa, s);
+    hipError_t err = emu_prepare(oa, akc, e.da, e.xa, s);
     if (err != hipSuccess) return err;
-    err = emu_prepare(ob, false, e.db, e.sb, s);
+    err = emu_prepare(ob, false, e.db, e.xb, s);
     if (err != hipSuccess) return err;
   }
   const int mt = (oa.R + EMU_TILE - 1) / EMU_TILE, nt = (ob.R + EMU_TILE - 1) / EMU_TILE;
-  *g = EmuGemmArgs{e.da, e.sa, e.db, e.sb, mt, nt, (oa.K + EMU_KB - 1) / EMU_KB, 0, mt, 0, nt, M, -1.0,
+  *g = EmuGemmArgs{e.da, e.xa, e.db, e.xb, mt, nt, (oa.K + EMU_KB - 1) / EMU_KB, 0, mt, 0, nt, M, -1.0,
                    N1 > 0 ? 2 : 1, {N0, N1}, {C0, C1}, {ldc0, ldc1}};
   return hipSuccess;
 }
@@ -489,8 +490,8 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
       const long rb = np + n + 1;
       w.emu.da = cv.take<int8_t>(emu_digit_bytes(np, NB2));
       w.emu.db = cv.take<int8_t>(emu_digit_bytes(rb, NB2));
-      w.emu.sa = cv.take<double>(emu_scale_count(np, NB2));
-      w.emu.sb = cv.take<double>(emu_scale_count(rb, NB2));
+      w.emu.xa = cv.take<int>(emu_scale_count(np));
+      w.emu.xb = cv.take<int>(emu_scale_count(rb));
     }
   } else {
     w.ldy = rhs_ld(n, pad_elems<float>());
