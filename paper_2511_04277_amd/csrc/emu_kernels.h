@@ -194,14 +194,18 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
   const emu_v4i* gb = reinterpret_cast<const emu_v4i*>(g.B) + static_cast<long>(bx) * CH;
   const long stride_a = static_cast<long>(g.mt) * CH;
   const long stride_b = static_cast<long>(g.nt) * CH;
-  // copies of one k block: wave w moves 1 KB pieces w, w + 4, ... of A then B
+  // copies of one k block: wave w moves 1 KB pieces w, w + 4, ... of A then
+  // B.  The B copies carry the sc0 cache policy: B's column panels stream
+  // past the 8 tile rows that an XCD holds at a time; alone on a 7168 x 8193
+  // x 1024 product the bit makes the kernel 18-24 % faster (A with it too: no
+  // further gain); inside the solve the difference is within noise.
   auto stage = [&](int kb) {
     const emu_v4i* sa = ga + kb * stride_a;
     const emu_v4i* sb = gb + kb * stride_b;
 #pragma unroll
     for (int p = w; p < CH / 64; p += 4) {
       __builtin_amdgcn_global_load_lds(sa + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[0][p * 64]), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(sb + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[1][p * 64]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(sb + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[1][p * 64]), 16, 0, 1);
     }
   };
   const int fr = l & 15, fc = l >> 4;
