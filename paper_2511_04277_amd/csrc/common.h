@@ -89,7 +89,7 @@ struct ProfScope {
 // after the wait on its previous record has been enqueued.
 struct SideStream {
   hipStream_t s2;
-  hipEvent_t ev[4];
+  hipEvent_t ev[6];
 };
 hipError_t side_stream(SideStream** out);
 bool lookahead_enabled();  // tuning: split trailing updates over the two streams

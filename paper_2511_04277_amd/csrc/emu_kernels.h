@@ -76,12 +76,12 @@ __device__ __forceinline__ double emu_load(const EmuOperand& op, int r, int k) {
   return op.X[q][rr * op.sr[q] + static_cast<long>(k) * op.sk[q]];
 }
 
-// Scale exponents e_r (max_k |X_rk| < 2^e_r; EMU_EXP_NONE for a zero row).
-// k-contiguous rows: one wave per row.
-static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int Rp, int* __restrict__ ex) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+// Scale exponents e_r (max_k |X_rk| < 2^e_r; EMU_EXP_NONE for a zero row) of
+// rows [r0, r1).  k-contiguous rows: one wave per row.
+static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
+  const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
-  if (r >= Rp) return;
+  if (r >= r1) return;
   double m = 0.0;
   for (int k = l; k < op.K; k += 64) m = fmax(m, fabs(emu_load(op, r, k)));
 #pragma unroll
@@ -94,10 +94,10 @@ static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int R
 // Rows contiguous in memory: a workgroup takes 256 rows x 64 k (each thread
 // one row, every load instruction 512 contiguous bytes) and merges its
 // exponents by atomic maxima; ex must hold EMU_EXP_NONE beforehand.
-static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int Rp, int* __restrict__ ex) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
+static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
+  const int r = r0 + blockIdx.x * 256 + threadIdx.x;
   const int k0 = blockIdx.y * EMU_KB;
-  if (r >= Rp) return;
+  if (r >= r1) return;
   double m = 0.0;
 #pragma unroll 8
   for (int k = k0; k < k0 + EMU_KB; ++k) m = fmax(m, fabs(emu_load(op, r, k)));
@@ -113,15 +113,16 @@ static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, 
   if (i < n) p[i] = v;
 }
 
-// Digits of one 64-row x 64-k block per workgroup.  The block's doubles are
-// read with 512-byte contiguous loads in whichever orientation the operand has
-// and transposed through LDS; thread t forms the S digits of 16 consecutive k
-// of row t / 4 (chunk c = t % 4), and a wave's stores of one slice are one
-// contiguous 1 KB piece of the block.
+// Digits of one 64-row x 64-k block per workgroup (row tile rt0 + blockIdx.x
+// of T).  The block's doubles are read with 512-byte contiguous loads in
+// whichever orientation the operand has and transposed through LDS; thread t
+// forms the S digits of 16 consecutive k of row t / 4 (chunk c = t % 4), and a
+// wave's stores of one slice are one contiguous 1 KB piece of the block.
 template <int S, bool KC>
-__global__ __launch_bounds__(256) void emu_split(EmuOperand op, const int* __restrict__ ex, int8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, const int* __restrict__ ex,
+                                                 int8_t* __restrict__ out) {
   __shared__ double tile[EMU_TILE][EMU_KB + 1];
-  const int rt = blockIdx.x, kb = blockIdx.y;
+  const int rt = rt0 + blockIdx.x, kb = blockIdx.y;
   const int t = threadIdx.x;
   const int r0 = rt * EMU_TILE, k0 = kb * EMU_KB;
 #pragma unroll
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(256) void emu_split(EmuOperand op, const int* __res
       dg[s].b[i] = static_cast<int8_t>(static_cast<int>(d));
     }
   }
-  emu_v4i* blk = reinterpret_cast<emu_v4i*>(out) + (static_cast<long>(kb) * gridDim.x + rt) * S * 256;
+  emu_v4i* blk = reinterpret_cast<emu_v4i*>(out) + (static_cast<long>(kb) * T + rt) * S * 256;
 #pragma unroll
   for (int s = 0; s < S; ++s) blk[emu_lds_idx(s, row, c)] = dg[s].v;
 }
@@ -280,19 +281,24 @@ inline size_t emu_digit_bytes(long R, long K) {
   return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB) * EMU_KB * EMU_S;
 }
 
-// Scale exponents and digits of one operand (kc: k contiguous in memory,
-// else rows).  ex receives one exponent per padded row.
-inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, hipStream_t s) {
-  const int T = (op.R + EMU_TILE - 1) / EMU_TILE, Rp = T * EMU_TILE;
+// Scale exponents and digits of the row tiles [t0, t1) of one operand (kc: k
+// contiguous in memory, else rows; t1 < 0: up to the last tile).  ex receives
+// one exponent per padded row; the digits land where the whole operand's
+// layout puts them, so disjoint tile ranges may be prepared by separate calls.
+inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, hipStream_t s, int t0 = 0,
+                              int t1 = -1) {
+  const int T = (op.R + EMU_TILE - 1) / EMU_TILE;
   const int nkb = (op.K + EMU_KB - 1) / EMU_KB;
-  if (T == 0 || nkb == 0) return hipSuccess;
+  if (t1 < 0 || t1 > T) t1 = T;
+  if (t0 >= t1 || nkb == 0) return hipSuccess;
+  const int r0 = t0 * EMU_TILE, r1 = t1 * EMU_TILE, nr = r1 - r0;
   if (kc) {
-    hipLaunchKernelGGL(emu_rowexp_kc, dim3((Rp + 3) / 4), dim3(256), 0, s, op, Rp, ex);
-    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(T, nkb), dim3(256), 0, s, op, ex, dig);
+    hipLaunchKernelGGL(emu_rowexp_kc, dim3((nr + 3) / 4), dim3(256), 0, s, op, r0, r1, ex);
+    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex, dig);
   } else {
-    hipLaunchKernelGGL(emu_fill_i32, dim3((Rp + 255) / 256), dim3(256), 0, s, ex, Rp, EMU_EXP_NONE);
-    hipLaunchKernelGGL(emu_rowexp_rc, dim3((Rp + 255) / 256, nkb), dim3(256), 0, s, op, Rp, ex);
-    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(T, nkb), dim3(256), 0, s, op, ex, dig);
+    hipLaunchKernelGGL(emu_fill_i32, dim3((nr + 255) / 256), dim3(256), 0, s, ex + r0, nr, EMU_EXP_NONE);
+    hipLaunchKernelGGL(emu_rowexp_rc, dim3((nr + 255) / 256, nkb), dim3(256), 0, s, op, r0, r1, ex);
+    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex, dig);
   }
   return hipGetLastError();
 }

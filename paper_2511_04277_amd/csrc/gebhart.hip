@@ -61,9 +61,11 @@ inline GemmArgs<T> update_args(const T* A, long lda, int M, int K) {
 }
 
 // Digit buffers of the int8-emulated products (RAD_PREC_FP64_I8).  One set
-// serves every product of a solve: the products that use it run on the
-// caller's stream, except the side-stream part of a factorization panel's
-// update, which the next panel joins before it prepares its own operands.
+// serves every product of a solve.  The products run on the caller's stream
+// except the side-stream part of a factorization panel's update, which the
+// next panel joins before it prepares its own operands; operand splits that
+// do not depend on the chain run on the side stream, ordered by events after
+// the last product that read the buffer they overwrite.
 struct EmuWork {
   int8_t* da;  // digits of op(A)
   int8_t* db;  // digits of B^T
@@ -71,24 +73,37 @@ struct EmuWork {
   int* xb;     // scale exponents of the columns of B
 };
 
-// Scales and digits of both operands of C -= op(A) B; g receives the launch
-// arguments for all tiles (callers narrow them).  C(i, j) is C0[i ldc0 + j]
-// for j < N0 and C1[i ldc1 + j - N0] after.
-inline hipError_t emu_product(const EmuWork& e, const EmuOperand& oa, bool akc, const EmuOperand& ob, int M, int N0,
-                              double* C0, long ldc0, int N1, double* C1, long ldc1, EmuGemmArgs* g, hipStream_t s) {
-  if (oa.K != ob.K || oa.K > EMU_MAX_K) return hipErrorInvalidValue;
-  {
-    ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0,
-                   (8.0 + EMU_S) * (static_cast<double>(oa.R) + ob.R) * static_cast<double>(oa.K));
-    hipError_t err = emu_prepare(oa, akc, e.da, e.xa, s);
-    if (err != hipSuccess) return err;
-    err = emu_prepare(ob, false, e.db, e.xb, s);
+// Scale exponents and digits of op(A) (if oa) and of B's row tiles
+// [bt0, bt1) (if ob; bt1 < 0: to the end), on stream s.
+inline hipError_t emu_split_ops(const EmuWork& e, const EmuOperand* oa, bool akc, const EmuOperand* ob, int bt0,
+                                int bt1, hipStream_t s) {
+  double elems = 0.0;
+  if (oa) elems += static_cast<double>(oa->R) * oa->K;
+  if (ob) {
+    const int T = (ob->R + EMU_TILE - 1) / EMU_TILE, t1 = bt1 < 0 ? T : std::min(bt1, T);
+    elems += std::max(0.0, std::min(static_cast<double>(ob->R), t1 * static_cast<double>(EMU_TILE)) -
+                               bt0 * static_cast<double>(EMU_TILE)) * ob->K;
+  }
+  ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0, (8.0 + EMU_S) * elems);
+  if (oa) {
+    if (oa->K > EMU_MAX_K) return hipErrorInvalidValue;
+    hipError_t err = emu_prepare(*oa, akc, e.da, e.xa, s);
     if (err != hipSuccess) return err;
   }
-  const int mt = (oa.R + EMU_TILE - 1) / EMU_TILE, nt = (ob.R + EMU_TILE - 1) / EMU_TILE;
-  *g = EmuGemmArgs{e.da, e.xa, e.db, e.xb, mt, nt, (oa.K + EMU_KB - 1) / EMU_KB, 0, mt, 0, nt, M, -1.0,
-                   N1 > 0 ? 2 : 1, {N0, N1}, {C0, C1}, {ldc0, ldc1}};
+  if (ob) {
+    if (ob->K > EMU_MAX_K) return hipErrorInvalidValue;
+    return emu_prepare(*ob, false, e.db, e.xb, s, bt0, bt1);
+  }
   return hipSuccess;
+}
+
+// Launch arguments for all tiles of C -= op(A) B (callers narrow them).
+// C(i, j) is C0[i ldc0 + j] for j < N0 and C1[i ldc1 + j - N0] after.
+inline EmuGemmArgs emu_args(const EmuWork& e, const EmuOperand& oa, const EmuOperand& ob, int M, int N0,
+                            double* C0, long ldc0, int N1 = 0, double* C1 = nullptr, long ldc1 = 0) {
+  const int mt = (oa.R + EMU_TILE - 1) / EMU_TILE, nt = (ob.R + EMU_TILE - 1) / EMU_TILE;
+  return EmuGemmArgs{e.da, e.xa, e.db, e.xb, mt, nt, (oa.K + EMU_KB - 1) / EMU_KB, 0, mt, 0, nt, M, -1.0,
+                     N1 > 0 ? 2 : 1, {N0, N1}, {C0, C1}, {ldc0, ldc1}};
 }
 
 inline hipError_t emu_run(const EmuGemmArgs& g, int K, hipStream_t s) {
@@ -108,8 +123,9 @@ inline EmuOperand emu_operand(const double* X, long sr, long sk, int R, int K, c
 // Step (3) of a factorization panel with int8-emulated products: the panel's
 // L block (rows c1.., columns c0..c1) and its U block together with the
 // right-hand-side rows (rows c0..c1, columns c1.. of K then of Y) are split
-// once; the next panel's columns are updated on s, the rest on s2 in row
-// chunks, with the same events as the FP64 path.
+// once - L and the next panel's columns of U on s, the rest of U and the
+// right-hand sides on s2 while s updates the next panel's columns; the rest
+// is updated on s2 in row chunks, with the same events as the FP64 path.
 hipError_t factor_update_emu(const EmuWork& ew, const Fact<double>& f, int c0, int c1, int c2, double* Y, long ldy,
                              int wy, hipStream_t s, hipStream_t s2, SideStream* ss) {
   const long ldk = f.ldk;
@@ -118,11 +134,17 @@ hipError_t factor_update_emu(const EmuWork& ew, const Fact<double>& f, int c0, i
   EmuOperand oa = emu_operand(kf + static_cast<long>(c1) * ldk + c0, ldk, 1, M, K);
   EmuOperand ob = emu_operand(kf + static_cast<long>(c0) * ldk + c1, 1, ldk, M, K,
                               Y ? Y + static_cast<long>(c0) * ldy : nullptr, 1, ldy, wyy);
-  EmuGemmArgs g;
-  hipError_t e = emu_product(ew, oa, true, ob, M, M, kf + static_cast<long>(c1) * ldk + c1, ldk, wyy,
-                             Y ? Y + static_cast<long>(c1) * ldy : nullptr, ldy, &g, s);
-  if (e != hipSuccess) return e;
   const int tx_next = (c2 - c1) / EMU_TILE;  // the next panel's column tiles
+  hipError_t e = emu_split_ops(ew, &oa, true, &ob, 0, tx_next, s);
+  if (e != hipSuccess) return e;
+  if (s2 != s) {  // s2's earlier reads of the buffers were joined into s before this step
+    e = stream_wait(s2, s, ss->ev[4]);
+    if (e != hipSuccess) return e;
+  }
+  e = emu_split_ops(ew, nullptr, false, &ob, tx_next, -1, s2);
+  if (e != hipSuccess) return e;
+  const EmuGemmArgs g = emu_args(ew, oa, ob, M, M, kf + static_cast<long>(c1) * ldk + c1, ldk, wyy,
+                                 Y ? Y + static_cast<long>(c1) * ldy : nullptr, ldy);
   EmuGemmArgs u = g;
   u.ntx = tx_next;
   e = emu_run(u, K, s);
@@ -360,6 +382,36 @@ struct PanelSweep {
   hipError_t join() { return stream_wait(s, s2, ss->ev[2]); }
 };
 
+// The factor operand of a panel's emulated update in the back and transposed
+// solves does not depend on the sweep: it is split on the side stream once
+// the previous update (the last reader of the digit buffer) has run, while
+// the caller's stream forms the panel's product.
+hipError_t emu_presplit(const EmuWork& ew, const EmuOperand& oa, bool akc, PanelSweep<double>& ps, bool* ready) {
+  *ready = false;
+  if (ps.s2 == ps.s) return hipSuccess;
+  hipError_t e = stream_wait(ps.s2, ps.s, ps.ss->ev[4]);
+  if (e != hipSuccess) return e;
+  e = emu_split_ops(ew, &oa, akc, nullptr, 0, 0, ps.s2);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ps.ss->ev[5], ps.s2);
+  if (e != hipSuccess) return e;
+  *ready = true;
+  return hipSuccess;
+}
+
+// C -= op(A) B for the rows outside the panel, B the panel's product in the
+// current scratch panel; op(A) split already on the side stream if a_ready.
+hipError_t emu_sweep_update(const EmuWork& ew, const EmuOperand& oa, bool akc, bool a_ready, const EmuOperand& ob,
+                            int M, int wy, double* C, long ldc, PanelSweep<double>& ps) {
+  hipError_t e = emu_split_ops(ew, a_ready ? nullptr : &oa, akc, &ob, 0, -1, ps.s);
+  if (e != hipSuccess) return e;
+  if (a_ready) {
+    e = hipStreamWaitEvent(ps.s, ps.ss->ev[5], 0);
+    if (e != hipSuccess) return e;
+  }
+  return emu_run(emu_args(ew, oa, ob, M, wy, C, ldc), oa.K, ps.s);
+}
+
 // Y <- U^{-1} Y in place (all np rows; padded rows stay zero): per panel from
 // the last, Y_p <- W_p Y_p, then the rows above take the panel's contribution
 // in one K = panel-width product.
@@ -374,17 +426,20 @@ hipError_t back_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, long lds
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    bool a_ready = false;
+    if (c0 > 0 && ew) {
+      if constexpr (std::is_same<T, double>::value)
+        e = emu_presplit(*ew, emu_operand(f.kf + c0, ldk, 1, c0, c1 - c0), true, ps, &a_ready);
+      if (e != hipSuccess) return e;
+    }
     e = ps.product(Wp, f.ldw, false, 1, c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c0 > 0 && ew) {
       if constexpr (std::is_same<T, double>::value) {
-        EmuGemmArgs g;
-        e = emu_product(*ew, emu_operand(f.kf + c0, ldk, 1, c0, c1 - c0), true,
-                        emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, 0, nullptr, 0, &g, s);
-        if (e != hipSuccess) return e;
-        e = emu_run(g, c1 - c0, s);
+        e = emu_sweep_update(*ew, emu_operand(f.kf + c0, ldk, 1, c0, c1 - c0), true, a_ready,
+                             emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, ps);
         if (e != hipSuccess) return e;
       }
     } else if (c0 > 0) {
@@ -409,18 +464,22 @@ hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, lo
   for (int c0 = 0; c0 < f.np; c0 += NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Wp = f.W + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    bool a_ready = false;
+    if (c1 < f.np && ew) {
+      if constexpr (std::is_same<T, double>::value)
+        e = emu_presplit(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk + c1, 1, ldk, f.np - c1, c1 - c0),
+                         false, ps, &a_ready);
+      if (e != hipSuccess) return e;
+    }
     e = ps.product(Wp, f.ldw, true, 2, c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c1 < f.np && ew) {
       if constexpr (std::is_same<T, double>::value) {
-        EmuGemmArgs g;
-        e = emu_product(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk + c1, 1, ldk, f.np - c1, c1 - c0),
-                        false, emu_operand(ps.cur, 1, lds, wy, c1 - c0), f.np - c1, wy,
-                        Y + static_cast<long>(c1) * ldy, ldy, 0, nullptr, 0, &g, s);
-        if (e != hipSuccess) return e;
-        e = emu_run(g, c1 - c0, s);
+        e = emu_sweep_update(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk + c1, 1, ldk, f.np - c1, c1 - c0),
+                             false, a_ready, emu_operand(ps.cur, 1, lds, wy, c1 - c0), f.np - c1, wy,
+                             Y + static_cast<long>(c1) * ldy, ldy, ps);
         if (e != hipSuccess) return e;
       }
     } else if (c1 < f.np) {  // rows below the panel: (U_{panel, c1..})^T Z_panel
@@ -437,17 +496,21 @@ hipError_t transposed_solve(const Fact<T>& f, T* Y, long ldy, int wy, T* scr, lo
   for (int c0 = last_c0; c0 >= 0; c0 -= NB2) {
     const int c1 = std::min(c0 + NB2, f.np);
     const T* Vp = f.V + static_cast<long>(c0 / NB2) * NB2 * f.ldw;
+    bool a_ready = false;
+    if (c0 > 0 && ew) {
+      if constexpr (std::is_same<T, double>::value)
+        e = emu_presplit(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk, 1, ldk, c0, c1 - c0), false, ps,
+                         &a_ready);
+      if (e != hipSuccess) return e;
+    }
     e = ps.product(Vp, f.ldw, true, 1, c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     e = ps.copy_back(c0, c1 - c0, Y, ldy, wy);
     if (e != hipSuccess) return e;
     if (c0 > 0 && ew) {
       if constexpr (std::is_same<T, double>::value) {
-        EmuGemmArgs g;
-        e = emu_product(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk, 1, ldk, c0, c1 - c0), false,
-                        emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, 0, nullptr, 0, &g, s);
-        if (e != hipSuccess) return e;
-        e = emu_run(g, c1 - c0, s);
+        e = emu_sweep_update(*ew, emu_operand(f.kf + static_cast<long>(c0) * ldk, 1, ldk, c0, c1 - c0), false,
+                             a_ready, emu_operand(ps.cur, 1, lds, wy, c1 - c0), c0, wy, Y, ldy, ps);
         if (e != hipSuccess) return e;
       }
     } else if (c0 > 0) {  // rows above the panel: (X_{panel, 0..c0})^T Lambda_panel
