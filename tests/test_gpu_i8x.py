@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from synth import workloads as W
-from tests.gpu_util import dev, host, need_gpu, torch
+from tests.gpu_util import dev, host, need_gpu, padded, torch
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-11
@@ -33,6 +33,32 @@ def test_solve_matches_oracle(n):
     err = np.abs(host(bd) - ref).max()
     print(f"[i8x] n={inst.n} max|dB|={err:.3e} stats={st}", flush=True)
     assert err <= TOL
+
+
+def test_padded_leading_dimension():
+    """F with ld = n + 7: the emulated products read the factors and
+    right-hand sides through the solver's own padded buffers either way."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(1500, seed=44)
+    eps, rho = inst.eps[0], inst.rho[0]
+    fd = padded(inst.f_noisy, inst.n + 7)
+    print(f"[i8x] padded ld n={inst.n}", flush=True)
+    bd, _, _ = rad.gebhart_ref(fd, dev(eps), dev(rho), precision="fp64_i8")
+    err = np.abs(host(bd) - oracle.gebhart_ref(inst.f_noisy, eps, rho)).max()
+    assert err <= TOL
+
+
+def test_invalid_optical_properties():
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    from paper_2511_04277_amd._lib import RadError
+    inst = W.box_with_n(1100, seed=45)
+    rho = inst.rho[0].copy()
+    rho[17] = 1.5
+    with pytest.raises(RadError) as e:
+        rad.gebhart_ref(dev(inst.f_noisy), dev(inst.eps[0]), dev(rho), precision="fp64_i8")
+    assert e.value.code == -2
 
 
 def test_rho_zero_gives_e_exactly():
