@@ -58,7 +58,6 @@ __device__ __forceinline__ int emu_lds_idx(int s, int r, int c) {
   return ((s * EMU_TILE + r) << 2) + (c ^ (((r >> 1) ^ (r >> 2)) & 3));
 }
 
-
 // Operand access: row r < R0 is element (r, k) at X[0][r sr[0] + k sk[0]],
 // row R0 <= r < R at X[1][(r - R0) sr[1] + k sk[1]]; both segments have the
 // same orientation (k contiguous, or rows contiguous).  Rows r >= R and
