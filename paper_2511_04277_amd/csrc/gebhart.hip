@@ -187,9 +187,15 @@ hipError_t factor_update_emu(const EmuWork& ew, const Fact<double>& f, int c0, i
 // side stream s2 meanwhile.  Panel p+1's row-block forward substitution waits
 // for that part (event), and the call joins s2 back into s at the end.  The
 // arithmetic and its order per element are the same as without the split.
+//
+// xs (nullable, np x NB elements): scratch for the L-block products
+// X = A21 D^-1.  With it they are written out of place and copied back, so
+// they take 64 x 64 tiles (two column tiles per row block, four times the
+// workgroups of the in-place 128 x 128 form) on the chain of diagonal blocks;
+// both forms round identically.
 template <class T>
 hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc, hipStream_t s,
-                          const EmuWork* ew = nullptr) {
+                          const EmuWork* ew = nullptr, T* xs = nullptr) {
   const long ldk = f.ldk;
   T* kf = f.kf;
   SideStream* ss = nullptr;
@@ -214,9 +220,16 @@ hipError_t factor_forward(const Fact<T>& f, T* Y, long ldy, int wy, Scalars* sc,
       if (r1 >= f.np) break;
       T* x = kf + static_cast<long>(r1) * ldk + k0;
       GemmArgs<T> a = gemm_args<T>(x, ldk, f.np - r1, NB, T(1), T(0));
-      gemm_add_segment<T>(a, dk, NB, x, ldk, NB);
-      a.inplace = 1;  // X overwrites the A21 it reads
-      RAD_GEMM(a, false);
+      if (xs) {
+        gemm_add_segment<T>(a, dk, NB, xs, NB, NB);
+        RAD_GEMM(a, false);
+        hipLaunchKernelGGL(copy_nb_cols<T>, dim3(static_cast<unsigned>(ceil_div(f.np - r1, 16))), dim3(256), 0, s,
+                           xs, static_cast<long>(NB), x, ldk, f.np - r1);
+      } else {
+        gemm_add_segment<T>(a, dk, NB, x, ldk, NB);
+        a.inplace = 1;  // X overwrites the A21 it reads
+        RAD_GEMM(a, false);
+      }
       if (r1 < c1) {
         GemmArgs<T> u = update_args<T>(x, ldk, f.np - r1, NB);
         gemm_add_segment<T>(u, kf + static_cast<long>(k0) * ldk + r1, ldk, kf + static_cast<long>(r1) * ldk + r1,
@@ -534,7 +547,8 @@ struct GebWork {
   double* part; // grad_eps partial sums (adjoint)
   EmuWork emu;  // digit buffers (RAD_PREC_FP64_I8)
   void* scr;    // (T) two panels of right-hand sides (2 NB2 x ldy), shared with
-                // the panel-inverse products (tri_tmp_elems, ld ldt)
+                // the panel-inverse products (tri_tmp_elems, ld ldt) and the
+                // factorization's L-block products (np x NB)
   long ldt;
   size_t bytes;
   bool ok;
@@ -641,7 +655,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     double* Y = static_cast<double*>(w.y);
     hipLaunchKernelGGL(geb_form<double>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
                        rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
-    RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s, ew));
+    RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, ni + 1, w.sc, s, ew, static_cast<double*>(w.scr)));
     RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
     RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s, ew));
     hipLaunchKernelGGL((copy_block<double, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, B,
@@ -651,7 +665,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
     float* Y = static_cast<float*>(w.y);
     hipLaunchKernelGGL(geb_form<float>, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, eps,
                        rho, f.kf, f.ldk, f.np, Y, w.ldy, w.sc);
-    RAD_HIP_CHECK(factor_forward<float>(f, Y, w.ldy, ni + 1, w.sc, s));
+    RAD_HIP_CHECK(factor_forward<float>(f, Y, w.ldy, ni + 1, w.sc, s, nullptr, static_cast<float*>(w.scr)));
     RAD_HIP_CHECK(panel_inverses<float>(f, static_cast<float*>(w.scr), w.ldt, s));
     RAD_HIP_CHECK(back_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
     if (ir_max > 0) {

@@ -485,6 +485,18 @@ copy_rows(const T* __restrict__ src, long lds, T* __restrict__ dst, long ldd, in
   for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[i * ldd + j] = src[i * lds + j];
 }
 
+// dst rows [0, rows) <- src, NB columns; 16 rows per workgroup, each thread
+// 8 consecutive entries
+template <class T>
+__global__ void __launch_bounds__(256)
+copy_nb_cols(const T* __restrict__ src, long lds, T* __restrict__ dst, long ldd, int rows) {
+  const long r = static_cast<long>(blockIdx.x) * 16 + (threadIdx.x >> 4);
+  if (r >= rows) return;
+  const int c = (threadIdx.x & 15) * (NB / 16);
+#pragma unroll
+  for (int j = 0; j < NB / 16; ++j) dst[r * ldd + c + j] = src[r * lds + c + j];
+}
+
 // dst (D, rows < n, cols <= n) <- src (S)
 template <class S, class D>
 __global__ void __launch_bounds__(256)
