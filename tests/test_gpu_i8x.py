@@ -21,11 +21,20 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-11
 
 
-@pytest.mark.parametrize("n", [1100, 2300, 3000])
+@pytest.mark.parametrize("n", [1025, 1100, 2049, 2300, 3000])
 def test_solve_matches_oracle(n):
+    """Ragged sizes, including one row past a 1024 panel (a 1-row trailing
+    update, padded to one 64-row tile) and one past two panels."""
     need_gpu()
     import paper_2511_04277_amd as rad
-    inst = W.box_with_n(n, seed=n)
+    if n in (1025, 2049):  # exact sizes: cut a larger box down to n faces, rows re-closed
+        base = W.box_with_n(n + 160, seed=n)
+        assert base.n > n
+        f = base.f_noisy[:n, list(range(n)) + [base.n]].copy()
+        f[:, n] = 1.0 - f[:, :n].sum(1)
+        inst = W.Instance(f"n{n}", f, f, base.area[:n], base.n_rays[:n], [base.eps[0][:n]], [base.rho[0][:n]])
+    else:
+        inst = W.box_with_n(n, seed=n)
     eps, rho = inst.eps[0], inst.rho[0]
     print(f"[i8x] solve n={inst.n}", flush=True)
     bd, _, st = rad.gebhart_ref(dev(inst.f_noisy), dev(eps), dev(rho), precision="fp64_i8")
