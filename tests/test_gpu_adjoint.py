@@ -97,6 +97,12 @@ def test_chimney_assembly_n4096_gradient():
     bd, fac, _ = rad.gebhart_ref(fd, dev(eps), dev(rho))
     ge, gr, _, _ = rad.gebhart_ref_adjoint(fac, fd, dev(rho), bd, dev(g))
     assert _rel(host(ge), rge) < 1e-10 and _rel(host(gr), rgr) < 1e-10
+    # the same gradients through the int8-emulated solve and transposed solve
+    b8, fac8, _ = rad.gebhart_ref(fd, dev(eps), dev(rho), precision="fp64_i8")
+    ge8, gr8, _, _ = rad.gebhart_ref_adjoint(fac8, fd, dev(rho), b8, dev(g))
+    print(f"[adjoint] chimney fp64_i8 rel err eps={_rel(host(ge8), rge):.2e} rho={_rel(host(gr8), rgr):.2e}",
+          flush=True)
+    assert _rel(host(ge8), rge) < 1e-10 and _rel(host(gr8), rgr) < 1e-10
     # central differences of J (through B only) on seeded faces, h = 1e-6
     rng = np.random.default_rng(44)
     h = 1e-6
