@@ -16,6 +16,8 @@ implements:
                   emissivity and reflectivity, by the transposed solve.
 * ``aggregate`` - multi-node surface relations (Sec. 5.2.3, eq. 5.6-5.7 and
                   eq. 5.28 for one-sided faces).
+* ``ahf``       - absorbed heat fluxes from REFs and direct heat fluxes
+                  (Sec. 4.2.3, eq. 4.6).
 
 All arithmetic is float64.  Functions whose result has a plain definition use
 that definition directly (a LAPACK solve, dense products, sums); the iterative
@@ -25,9 +27,10 @@ from .enforce import closure_step, enforce_vf, reciprocity_step, kappa_fracvar, 
 from .gebhart import form_k_e, gebhart_ref, ref_closure_residual, ref_reciprocity_residual
 from .adjoint import gebhart_ref_adjoint
 from .aggregate import aggregate_nodes
+from .ahf import absorbed_flux
 
 __all__ = [
     "closure_step", "enforce_vf", "reciprocity_step", "kappa_fracvar", "mae",
     "form_k_e", "gebhart_ref", "ref_closure_residual", "ref_reciprocity_residual",
-    "gebhart_ref_adjoint", "aggregate_nodes",
+    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux",
 ]
