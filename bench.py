@@ -11,9 +11,11 @@ is one pass of the whole hot path over that input, all on the GPU:
   net radiative loss to space) -> REF aggregation 8192 -> 2048 -> 128 nodes.
 
 It yields one REF matrix, so value = REF matrices per second.  The Gebhart
-solve is also timed alone in FP64 and in FP32 + FP64 refinement, each checked
-against the FP64 CPU oracle on the same enforced F (max |dB| must be
-<= 1e-10); the step uses the faster of the two that meets that bound.
+solve is also timed alone in FP64, in FP64 with int8 digit products and in
+FP32 + FP64 refinement, each checked against the FP64 CPU oracle on the same
+enforced F (max |dB| must be <= 1e-10); the step uses the fastest variant
+that meets that bound.  After the timed steps, the absorbed heat fluxes of
+eq. 4.6 (16 load cases) are timed on the step's REFs, outside the step.
 
 Prints one JSON line (see the keys at the end of main()).
 """
@@ -32,6 +34,7 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "int8": 5000.0}  # MI355X dense MFMA (int8: TOP/s)
 I8X_PRODUCTS = 28  # digit products per emulated FP64 product (7 digits per operand, pairs s + t < 7)
 PEAK_HBM_GBS = 8000.0
+AHF_CASES = 16  # load cases of the absorbed-flux measurement (the entry point's maximum)
 SIGMA = 5.67e-8
 T_SPACE = 3.0
 ENF_TOL = 1e-13
@@ -332,6 +335,10 @@ def main() -> int:
     sw = profs_all[L.PROFILE_KINDS.index("enforce_sweep")]
     if sw.launches:
         kern["enforce_sweep"]["hbm_frac"] = (sw.bytes / (sw.total_ms * 1e-3) / 1e9) / PEAK_HBM_GBS
+    ahf = absorbed_flux_timing(rad, L, lib, slots[0]["B"], eps, rho, area, d(W.rng_for(8192, 2).uniform(
+        0.0, 1400.0, (n, AHF_CASES))))
+    log(f"absorbed flux ({AHF_CASES} cases): {ahf['ms']:.3f} ms per call, kernel {ahf['kernel_us']:.1f} us "
+        f"= {ahf['gbs']:.0f} GB/s ({100 * ahf['hbm_frac']:.0f}% of HBM)")
 
     # ---- CPU baseline: the oracle on a bounded sample of the same step ----
     if not args.no_cpu_baseline:
@@ -383,9 +390,40 @@ def main() -> int:
         "kernels": kern,
         "kernels_source": "one untimed step before the timed region with every profiled kind bracketed by HIP events",
         "ref_residuals": {"closure": float(chk_h[0]), "reciprocity": float(chk_h[1])},
+        "absorbed_flux": ahf,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def absorbed_flux_timing(rad, L, lib, B, eps, rho, area, qd, reps: int = 20) -> dict:
+    """Eq. 4.6 on the step's REFs (outside the step): whole calls timed with
+    events on the launching stream, the B-reading kernel bracketed by the
+    library's own events; algorithmic bytes = the N x N block of B."""
+    import torch
+    n, m = qd.shape
+    rad.absorbed_flux(B, eps, rho, area, qd)
+    torch.cuda.synchronize()
+    NK = len(L.PROFILE_KINDS)
+    L.check(lib.rad_profile_kinds(1 << L.PROFILE_KINDS.index("ahf")), "rad_profile_kinds")
+    lib.rad_profile_read((L.RadKernelProfile * NK)(), NK)
+    lib.rad_profile_enable(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rad.absorbed_flux(B, eps, rho, area, qd)
+    e1.record()
+    torch.cuda.synchronize()
+    lib.rad_profile_enable(0)
+    profs = (L.RadKernelProfile * NK)()
+    L.check(lib.rad_profile_read(profs, NK), "rad_profile_read")
+    L.check(lib.rad_profile_kinds(0xFFFFFFFF), "rad_profile_kinds")
+    p = profs[L.PROFILE_KINDS.index("ahf")]
+    k_s = p.total_ms * 1e-3 / p.launches
+    gbs = p.bytes / p.launches / k_s / 1e9
+    return {"n": n, "load_cases": m, "ms": e0.elapsed_time(e1) / reps, "kernel": "ahf_partial<16>",
+            "kernel_us": 1e6 * k_s, "algorithmic_bytes_per_launch": p.bytes / p.launches, "gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm"}
 
 
 def run_batch64(args) -> int:

@@ -202,6 +202,26 @@ int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                             double* group_weight, void* work, size_t work_bytes,
                             rad_stats* stats, void* stream);
 
+/* ---- absorbed heat fluxes ----------------------------------------------- */
+/*
+ * Absorbed heat fluxes from REFs and direct heat fluxes (Sec. 4.2.3,
+ * eq. 4.6), for m load cases at once:
+ *   Qa[i][c] = A_i eps_i Qd[i][c] + sum_{j<n} B_ji A_j rho_j Qd[j][c].
+ * B: n x (n+1) REF matrix (ld ldb; the space column is not read); eps, rho,
+ * area: n values; Qd: n x m direct heat flux per unit area (ld ldq >= m);
+ * Qa: n x m absorbed power (ld lda >= m); 1 <= m <= RAD_AHF_MAX_CASES.  All
+ * device pointers.  B is read once; each sum over j runs in a fixed order
+ * (bitwise reproducible).
+ * work: >= rad_absorbed_flux_workspace_bytes(n, m), 256-byte aligned.
+ */
+#define RAD_AHF_MAX_CASES 16
+size_t rad_absorbed_flux_workspace_bytes(int64_t n, int64_t m);
+int32_t rad_absorbed_flux(const double* B, int64_t n, int64_t ldb,
+                          const double* eps, const double* rho,
+                          const double* area, const double* Qd, int64_t m,
+                          int64_t ldq, double* Qa, int64_t lda, void* work,
+                          size_t work_bytes, void* stream);
+
 /* ---- batches of models ------------------------------------------------ */
 /*
  * Many independent open models of uneven size, each with one or two spectral
@@ -314,7 +334,8 @@ int32_t rad_tuning_set(const rad_tuning* in);
 #define RAD_PROF_GEMM_F32_T 6    /* FP32 MFMA GEMM with transposed A (adjoint)       */
 #define RAD_PROF_GEMM_I8X 7      /* FP64 product emulated with int8 MFMA digit products */
 #define RAD_PROF_I8X_SPLIT 8     /* operand scaling and digit split for those products */
-#define RAD_PROF_KINDS 9
+#define RAD_PROF_AHF 9           /* absorbed heat fluxes (transposed product with B)    */
+#define RAD_PROF_KINDS 10
 
 typedef struct rad_kernel_profile {
   int64_t launches;

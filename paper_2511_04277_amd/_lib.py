@@ -80,7 +80,7 @@ class RadTuning(ctypes.Structure):
 
 
 PROFILE_KINDS = ["gemm_f64", "gemm_f32", "enforce_sweep", "diag_inverse", "aggregate", "gemm_f64_t",
-                 "gemm_f32_t", "gemm_i8x", "i8x_split"]
+                 "gemm_f32_t", "gemm_i8x", "i8x_split", "ahf"]
 
 
 class RadError(RuntimeError):
@@ -112,6 +112,8 @@ SIGNATURES = {
     "rad_gebhart_ref_adjoint": (_I32, [_P, _SZ, _I32, _P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P,
                                       _I64, _D, _I32, _P, _SZ, _STATS, _P]),
     "rad_aggregate_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_absorbed_flux_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_absorbed_flux": (_I32, [_P, _I64, _I64, _P, _P, _P, _P, _I64, _I64, _P, _I64, _P, _SZ, _P]),
     "rad_aggregate_nodes": (_I32, [_P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _SZ, _STATS, _P]),
     "rad_batch_plan_create": (_I32, [ctypes.POINTER(RadInstance), _I32, _I32, _I32, ctypes.POINTER(_P),
                                      ctypes.POINTER(_SZ)]),

@@ -107,6 +107,33 @@ def aggregate_nodes(X: torch.Tensor, weight: torch.Tensor, group: torch.Tensor, 
     return out, gw
 
 
+def absorbed_flux(B: torch.Tensor, eps: torch.Tensor, rho: torch.Tensor, area: torch.Tensor, Qd: torch.Tensor,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Absorbed heat fluxes (eq. 4.6): Qa = diag(A eps) Qd + B_sq^T diag(A rho) Qd.
+
+    Qd: direct heat flux per unit area, n values or n x m load cases (m <= 16);
+    returns the absorbed power with the same shape.
+    """
+    n = B.shape[0]
+    ldb = _mat(B, "B", n, n + 1)
+    for v, nm in ((eps, "eps"), (rho, "rho"), (area, "area")):
+        _vec(v, nm, n)
+    vec = Qd.dim() == 1
+    q = Qd.unsqueeze(1) if vec else Qd
+    m = q.shape[1]
+    ldq = _mat(q, "Qd", n, m)
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float64, device=B.device)
+    o = out.unsqueeze(1) if out.dim() == 1 else out
+    lda = _mat(o, "Qa", n, m)
+    lib = L.lib()
+    work = WORKSPACE.get(B.device, "ahf", lib.rad_absorbed_flux_workspace_bytes(n, m))
+    code = lib.rad_absorbed_flux(_vp(B), n, ldb, _vp(eps), _vp(rho), _vp(area), _vp(q), m, ldq, _vp(o), lda,
+                                 _vp(work), work.numel(), _stream(B.device))
+    L.check(code, "rad_absorbed_flux")
+    return out[:, 0] if (vec and out.dim() == 2) else out
+
+
 class Factors:
     """Device buffer holding a factorization of K (reused by the adjoint)."""
 
