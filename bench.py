@@ -421,7 +421,7 @@ def absorbed_flux_timing(rad, L, lib, B, eps, rho, area, qd, reps: int = 20) -> 
     p = profs[L.PROFILE_KINDS.index("ahf")]
     k_s = p.total_ms * 1e-3 / p.launches
     gbs = p.bytes / p.launches / k_s / 1e9
-    return {"n": n, "load_cases": m, "ms": e0.elapsed_time(e1) / reps, "kernel": "ahf_partial<16>",
+    return {"n": n, "load_cases": m, "ms": e0.elapsed_time(e1) / reps, "kernel": "ahf_partial<16, 2, 4, true>",
             "kernel_us": 1e6 * k_s, "algorithmic_bytes_per_launch": p.bytes / p.launches, "gbs": gbs,
             "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm"}
 

@@ -4,11 +4,14 @@
 //   Qa[i][c] = A_i eps_i Qd[i][c] + sum_j B_ji A_j rho_j Qd[j][c]
 //
 // The sum is a transposed product with the N x N block of B, which is read
-// once (HBM-bound).  ahf_partial: workgroup = (256 consecutive faces i, one
-// chunk of rows j); each thread owns face i and sums B_ji w_jc over its
-// chunk's rows, with w_jc = A_j rho_j Qd[j][c] staged in LDS, so every load
-// instruction reads 2 KB of one row of B.  ahf_final adds the direct term and
-// the chunk sums in chunk order (fixed order: bitwise reproducible).
+// once (HBM-bound).  ahf_weights forms w_jc = A_j rho_j Qd[j][c] (zero-padded
+// to MC cases).  ahf_partial: one wave per (64 CI consecutive faces, chunk of
+// rows j); a lane owns CI faces i, 64 apart, and sums B_ji w_jc over the
+// chunk's rows.  w_jc is the same for every lane, so it comes through scalar
+// loads (no LDS, no barriers) and feeds the FMAs as a scalar operand; each row
+// of B is CI 512-byte vector loads per wave, U rows in flight.  ahf_final adds
+// the direct term and the chunk sums in chunk order (fixed order: bitwise
+// reproducible).
 #include <algorithm>
 
 #include "common.h"
@@ -17,42 +20,89 @@ namespace rad {
 namespace {
 
 constexpr int AHF_THREADS = 256;
+constexpr int AHF_WAVE = 64;
 constexpr int AHF_MAX_CHUNKS = 64;
-constexpr int AHF_ROWS = 128;  // rows of w staged in LDS at a time
+constexpr int AHF_TARGET_WAVES = 2048;  // 8 per CU
+
+// Per padded case count MC: U rows of B in flight per lane and CI faces per
+// lane (measured at N = 8192: MC <= 8 streams B at 6.0-6.3 TB/s with two
+// faces per lane; MC = 16 is bound by the scalar weight loads and prefers
+// four faces per lane, so each weight feeds four FMAs).  B is streamed once,
+// so its loads are nontemporal.
+template <int MC>
+struct AhfShape {
+  static constexpr int U = MC >= 16 ? 2 : MC >= 8 ? 4 : 8;
+  static constexpr int CI = MC >= 16 ? 4 : 2;
+};
 
 template <int MC>
 __global__ void __launch_bounds__(AHF_THREADS)
-ahf_partial(const double* __restrict__ B, long ldb, int n, const double* __restrict__ rho,
-            const double* __restrict__ area, const double* __restrict__ qd, long ldq, int m, int rows,
+ahf_weights(int n, const double* __restrict__ rho, const double* __restrict__ area, const double* __restrict__ qd,
+            long ldq, int m, double* __restrict__ w) {
+  const long t = static_cast<long>(blockIdx.x) * AHF_THREADS + threadIdx.x;
+  if (t >= static_cast<long>(n) * MC) return;
+  const int j = static_cast<int>(t / MC), c = static_cast<int>(t % MC);
+  w[t] = c < m ? area[j] * rho[j] * qd[static_cast<long>(j) * ldq + c] : 0.0;
+}
+
+template <int MC, int U = AhfShape<MC>::U, int CI = AhfShape<MC>::CI, bool NT = true>
+__global__ void __launch_bounds__(AHF_WAVE)
+ahf_partial(const double* __restrict__ B, long ldb, int n, const double* __restrict__ w, int rows,
             double* __restrict__ part) {
-  __shared__ double w[AHF_ROWS][MC];
-  const int i = blockIdx.x * AHF_THREADS + threadIdx.x;
+  // lane owns faces i0 + 64 q, q < CI (lanes past the last face load a valid
+  // column and store nothing)
+  const int i0 = blockIdx.x * AHF_WAVE * CI + threadIdx.x;
   const int j0 = blockIdx.y * rows, j1 = min(n, j0 + rows);
-  double acc[MC];
+  double acc[CI][MC];
+  const double* bcol[CI];
 #pragma unroll
-  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
-  for (int jb = j0; jb < j1; jb += AHF_ROWS) {
-    const int nr = min(AHF_ROWS, j1 - jb);
-    __syncthreads();  // the previous block of w is consumed
-    for (int e = threadIdx.x; e < nr * MC; e += AHF_THREADS) {
-      const int r = e / MC, c = e % MC, j = jb + r;
-      w[r][c] = c < m ? area[j] * rho[j] * qd[static_cast<long>(j) * ldq + c] : 0.0;
-    }
-    __syncthreads();
-    if (i < n) {
-      const double* bj = B + static_cast<long>(jb) * ldb + i;
-#pragma unroll 4
-      for (int r = 0; r < nr; ++r) {
-        const double b = bj[static_cast<long>(r) * ldb];
+  for (int q = 0; q < CI; ++q) {
+    bcol[q] = B + min(i0 + AHF_WAVE * q, n - 1);
 #pragma unroll
-        for (int c = 0; c < MC; ++c) acc[c] = fma(b, w[r][c], acc[c]);
+    for (int c = 0; c < MC; ++c) acc[q][c] = 0.0;
+  }
+  auto load = [&](int q, int j) {
+    const double* p = bcol[q] + static_cast<long>(j) * ldb;
+    return NT ? __builtin_nontemporal_load(p) : *p;
+  };
+  int j = j0;
+  for (; j + U <= j1; j += U) {
+    double b[U][CI];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < CI; ++q) b[u][q] = load(q, j + u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double* wj = w + static_cast<long>(j + u) * MC;
+#pragma unroll
+      for (int c = 0; c < MC; ++c) {
+        const double wc = wj[c];
+#pragma unroll
+        for (int q = 0; q < CI; ++q) acc[q][c] = fma(b[u][q], wc, acc[q][c]);
       }
     }
   }
-  if (i >= n) return;
-  double* p = part + (static_cast<long>(blockIdx.y) * n + i) * MC;
+  for (; j < j1; ++j) {
+    double b[CI];
 #pragma unroll
-  for (int c = 0; c < MC; ++c) p[c] = acc[c];
+    for (int q = 0; q < CI; ++q) b[q] = load(q, j);
+    const double* wj = w + static_cast<long>(j) * MC;
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      const double wc = wj[c];
+#pragma unroll
+      for (int q = 0; q < CI; ++q) acc[q][c] = fma(b[q], wc, acc[q][c]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CI; ++q) {
+    const int i = i0 + AHF_WAVE * q;
+    if (i >= n) break;
+    double* p = part + (static_cast<long>(blockIdx.y) * n + i) * MC;
+#pragma unroll
+    for (int c = 0; c < MC; ++c) p[c] = acc[q][c];
+  }
 }
 
 template <int MC>
@@ -64,25 +114,45 @@ ahf_final(const double* __restrict__ part, int chunks, int n, const double* __re
   if (t >= static_cast<long>(n) * m) return;
   const int i = static_cast<int>(t / m), c = static_cast<int>(t % m);
   double s = area[i] * eps[i] * qd[static_cast<long>(i) * ldq + c];
-  for (int k = 0; k < chunks; ++k) s += part[(static_cast<long>(k) * n + i) * MC + c];
+  const double* p = part + static_cast<long>(i) * MC + c;
+  const long stride = static_cast<long>(n) * MC;
+  int k = 0;
+  for (; k + 8 <= chunks; k += 8) {  // eight loads in flight, added in chunk order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(k + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; k < chunks; ++k) s += p[k * stride];
   qa[static_cast<long>(i) * lda + c] = s;
 }
 
 int cases_pad(int64_t m) { return m <= 1 ? 1 : m <= 2 ? 2 : m <= 4 ? 4 : m <= 8 ? 8 : 16; }
 
-int ahf_chunks(int64_t n) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(AHF_MAX_CHUNKS, ceil_div(n, AHF_ROWS))));
+int ahf_chunks(int64_t n, int mc) {
+  const int64_t col_waves = ceil_div(n, AHF_WAVE * (mc >= 16 ? AhfShape<16>::CI : AhfShape<1>::CI));
+  const int64_t by_waves = std::max<int64_t>(1, AHF_TARGET_WAVES / col_waves);
+  const int64_t by_rows = std::max<int64_t>(1, n / AHF_WAVE);  // at least 64 rows per chunk
+  return static_cast<int>(std::min<int64_t>({AHF_MAX_CHUNKS, by_waves, by_rows}));
 }
+
+// workspace: w (n x MC) then the chunk sums (chunks x n x MC), both 256-byte aligned
+size_t ahf_w_bytes(int64_t n, int mc) { return static_cast<size_t>(ceil_div(n * mc * 8, 256) * 256); }
 
 template <int MC>
 void ahf_launch(const double* B, long ldb, int n, const double* eps, const double* rho, const double* area,
-                const double* qd, long ldq, int m, double* qa, long lda, double* part, hipStream_t s) {
-  const int chunks = ahf_chunks(n);
+                const double* qd, long ldq, int m, double* qa, long lda, char* work, hipStream_t s) {
+  const int chunks = ahf_chunks(n, MC);
   const int rows = static_cast<int>(ceil_div(n, chunks));
+  double* w = reinterpret_cast<double*>(work);
+  double* part = reinterpret_cast<double*>(work + ahf_w_bytes(n, MC));
+  hipLaunchKernelGGL((ahf_weights<MC>), dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(n) * MC, AHF_THREADS))),
+                     dim3(AHF_THREADS), 0, s, n, rho, area, qd, ldq, m, w);
   {
     ProfScope prof(s, RAD_PROF_AHF, 2.0 * static_cast<double>(n) * n * m, 8.0 * static_cast<double>(n) * n);
-    hipLaunchKernelGGL((ahf_partial<MC>), dim3(static_cast<unsigned>(ceil_div(n, AHF_THREADS)), chunks),
-                       dim3(AHF_THREADS), 0, s, B, ldb, n, rho, area, qd, ldq, m, rows, part);
+    hipLaunchKernelGGL((ahf_partial<MC>), dim3(static_cast<unsigned>(ceil_div(n, AHF_WAVE * AhfShape<MC>::CI)), chunks),
+                       dim3(AHF_WAVE), 0, s, B, ldb, n, w, rows, part);
   }
   hipLaunchKernelGGL((ahf_final<MC>), dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(n) * m, AHF_THREADS))),
                      dim3(AHF_THREADS), 0, s, part, chunks, n, eps, area, qd, ldq, m, qa, lda);
@@ -95,7 +165,8 @@ using namespace rad;
 
 extern "C" size_t rad_absorbed_flux_workspace_bytes(int64_t n, int64_t m) {
   if (n < 1 || m < 1 || m > RAD_AHF_MAX_CASES) return 0;
-  return static_cast<size_t>(ahf_chunks(n)) * static_cast<size_t>(n) * cases_pad(m) * sizeof(double);
+  const int mc = cases_pad(m);
+  return ahf_w_bytes(n, mc) + static_cast<size_t>(ahf_chunks(n, mc)) * static_cast<size_t>(n) * mc * sizeof(double);
 }
 
 extern "C" int32_t rad_absorbed_flux(const double* B, int64_t n, int64_t ldb, const double* eps,
@@ -112,13 +183,13 @@ extern "C" int32_t rad_absorbed_flux(const double* B, int64_t n, int64_t ldb, co
               RAD_EWORKSPACE, "rad_absorbed_flux: workspace too small or not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ni = static_cast<int>(n), mi = static_cast<int>(m);
-  double* part = static_cast<double*>(work);
+  char* ws = static_cast<char*>(work);
   switch (cases_pad(m)) {
-    case 1: ahf_launch<1>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, part, s); break;
-    case 2: ahf_launch<2>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, part, s); break;
-    case 4: ahf_launch<4>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, part, s); break;
-    case 8: ahf_launch<8>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, part, s); break;
-    default: ahf_launch<16>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, part, s); break;
+    case 1: ahf_launch<1>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, ws, s); break;
+    case 2: ahf_launch<2>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, ws, s); break;
+    case 4: ahf_launch<4>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, ws, s); break;
+    case 8: ahf_launch<8>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, ws, s); break;
+    default: ahf_launch<16>(B, ldb, ni, eps, rho, area, Qd, ldq, mi, Qa, lda, ws, s); break;
   }
   RAD_HIP_CHECK(hipGetLastError());
   return RAD_OK;

@@ -92,3 +92,29 @@ def test_full_size_open_cube_n5120():
     ref, info = oracle.enforce_vf(inst.f_noisy, inst.area, inst.n_rays, "fracvar", tol=0.0, max_iter=iters)
     assert np.abs(g - ref).max() <= TOL
     assert np.abs(g.sum(1) - 1).max() < 1e-14
+
+
+def test_ref_level_enforcement_with_eps_area_weights():
+    """REF-level enforcement: the same iteration run on a REF matrix B with
+    weights eps_i A_i in place of A_i, since REF reciprocity reads
+    eps_i A_i B_ij = eps_j A_j B_ji and REF closure sum_j B_ij = 1 (Sec. 4.2.3,
+    eq. 4.3-4.4).  B is the oracle's Gebhart solve on the noisy, unenforced F."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    inst = W.box_with_n(330, seed=6)
+    eps, rho = inst.eps[0], inst.rho[0]
+    b = oracle.gebhart_ref(inst.f_noisy, eps, rho)
+    w = eps * inst.area
+    iters = 25
+    print(f"[enforce] REF level n={inst.n}", flush=True)
+    B = dev(b)
+    st = rad.enforce_vf_(B, dev(w), None, kappa="half", tol=0.0, max_iter=iters)
+    ref, info = oracle.enforce_vf(b, w, None, "half", tol=0.0, max_iter=iters)
+    assert st["iters"] == iters
+    assert np.abs(host(B) - ref).max() <= TOL
+    # to tolerance: the REF checks of the enforced B meet it
+    B = dev(b)
+    st = rad.enforce_vf_(B, dev(w), None, kappa="half", tol=1e-13, max_iter=400)
+    assert st["converged"] == 1
+    chk = host(rad.ref_check(B, dev(eps), dev(inst.area)))
+    assert chk[0] <= 1e-13 and chk[1] <= 1e-12 * np.abs(w[:, None] * b[:, :inst.n]).max()
