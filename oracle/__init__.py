@@ -18,6 +18,8 @@ implements:
                   eq. 5.28 for one-sided faces).
 * ``ahf``       - absorbed heat fluxes from REFs and direct heat fluxes
                   (Sec. 4.2.3, eq. 4.6).
+* ``steady``    - radiation-only steady-state node temperatures (Sec. 3.4.4,
+                  eq. 3.12-3.14 with GR from REFs, eq. 4.2).
 
 All arithmetic is float64.  Functions whose result has a plain definition use
 that definition directly (a LAPACK solve, dense products, sums); the iterative
@@ -28,9 +30,10 @@ from .gebhart import form_k_e, gebhart_ref, ref_closure_residual, ref_reciprocit
 from .adjoint import gebhart_ref_adjoint
 from .aggregate import aggregate_nodes
 from .ahf import absorbed_flux
+from .steady import steady_temperature
 
 __all__ = [
     "closure_step", "enforce_vf", "reciprocity_step", "kappa_fracvar", "mae",
     "form_k_e", "gebhart_ref", "ref_closure_residual", "ref_reciprocity_residual",
-    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux",
+    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux", "steady_temperature",
 ]
