@@ -339,6 +339,10 @@ def main() -> int:
         0.0, 1400.0, (n, AHF_CASES))))
     log(f"absorbed flux ({AHF_CASES} cases): {ahf['ms']:.3f} ms per call, kernel {ahf['kernel_us']:.1f} us "
         f"= {ahf['gbs']:.0f} GB/s ({100 * ahf['hbm_frac']:.0f}% of HBM)")
+    steady = steady_timing(rad, slots[0]["B"], eps, rho, area, w_ref, prec, W.rng_for(8192, 2).uniform(
+        0.0, 1400.0, (n, AHF_CASES)), d)
+    log(f"steady temperatures ({AHF_CASES} cases, {prec}): {steady['ms']:.2f} ms, "
+        f"{steady['tflops_fp64_equivalent']:.1f} TFLOP/s FP64-equivalent")
 
     # ---- CPU baseline: the oracle on a bounded sample of the same step ----
     if not args.no_cpu_baseline:
@@ -391,9 +395,38 @@ def main() -> int:
         "kernels_source": "one untimed step before the timed region with every profiled kind bracketed by HIP events",
         "ref_residuals": {"closure": float(chk_h[0]), "reciprocity": float(chk_h[1])},
         "absorbed_flux": ahf,
+        "steady_temperature": steady,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def steady_timing(rad, B, eps, rho, area, w, prec, qd_host, d, reps: int = 3) -> dict:
+    """Radiation-only steady node temperatures (eq. 3.12-3.14, GR = sigma eps A B)
+    on the step's REFs with the absorbed fluxes of eq. 4.6 as heat inputs,
+    outside the step; every face is a node, all free.  Flops: the LU of the
+    n x n balance (2/3 n^3) and the two triangular solves on its 64-column
+    right-hand-side tile."""
+    import numpy as np
+    import torch
+    n = B.shape[0]
+    qa = rad.absorbed_flux(B, eps, rho, area, d(qd_host))
+    T, fac, st = rad.steady_temperature(B, w, qa, precision=prec)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rad.steady_temperature(B, w, qa, precision=prec, factors=fac, out=T, want_stats=False)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    flops = 2.0 / 3.0 * n ** 3 + 2.0 * n * n * 64
+    th = T.cpu().numpy()
+    return {"n": n, "load_cases": int(qa.shape[1]), "precision": prec, "ms": ms,
+            "tflops_fp64_equivalent": flops / (ms * 1e-3) / 1e12, "device_status": st["device_status"],
+            "t_min_k": float(th.min()), "t_max_k": float(th.max())}
 
 
 def absorbed_flux_timing(rad, L, lib, B, eps, rho, area, qd, reps: int = 20) -> dict:

@@ -202,6 +202,46 @@ int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                             double* group_weight, void* work, size_t work_bytes,
                             rad_stats* stats, void* stream);
 
+/* ---- steady-state node temperatures ------------------------------------ */
+/*
+ * Radiation-only steady state of the node heat equation (Sec. 3.4.4,
+ * eq. 3.14 with dT/dt = 0 and no conductive couplings), with radiative
+ * couplings from REFs, GR_ij = sigma w_i Y_ij (eq. 4.2, w_i = eps_i A_i):
+ * every free node i balances its heat input against the power it radiates
+ * (eq. 3.12-3.13),
+ *   sum_{j<n} GR_ij (T_i^4 - T_j^4) + GR_i,space (T_i^4 - t_space^4) = Q_i,
+ * for m load cases at once.  Linear in x = T^4: one LU solve (block LDU
+ * without pivoting, the Gebhart solve's kernels) of the balance rows scaled
+ * by 1 / (sigma w_i); nodes with a prescribed temperature keep it.
+ * Y: n x (n+1) REF matrix, face or node level (ld ldy; column n = space),
+ *   entries >= 0; weight: n values w_i > 0 (eps_i A_i, or W_G after
+ *   aggregation); Q: n x m heat input per node in W (ld ldq >= m);
+ *   t_fixed: n values (nullable = all free): > 0 holds node i at that
+ *   temperature, 0 leaves it free; t_space >= 0 (K); sigma > 0 (the
+ *   Stefan-Boltzmann constant in the caller's units); T: n x m output (K,
+ *   ld ldt >= m); 1 <= m <= RAD_STEADY_MAX_CASES.  All device pointers.
+ * precision: RAD_PREC_FP64 or RAD_PREC_FP64_I8 (as in rad_gebhart_ref).
+ * factors: >= rad_gebhart_factor_bytes(n, precision), receives the
+ *   factorization of the balance matrix; work: >=
+ *   rad_steady_temperature_workspace_bytes(n, precision); both 256-byte
+ *   aligned.
+ * Device checks (reported when ``stats`` is non-NULL, which synchronises
+ * the stream): negative or non-finite Y, w, Q or t_fixed, or a free node
+ * whose T^4 comes out <= 0 (the heat input is a sink no temperature can
+ * balance): RAD_ENONFINITE, with T = NaN there; a free node with no path to
+ * space or to a fixed node (singular balance): RAD_ESINGULAR.
+ */
+#define RAD_STEADY_MAX_CASES 64
+size_t rad_steady_temperature_workspace_bytes(int64_t n, int32_t precision);
+int32_t rad_steady_temperature(const double* Y, int64_t n, int64_t ldy,
+                               const double* weight, const double* Q,
+                               int64_t m, int64_t ldq, const double* t_fixed,
+                               double t_space, double sigma, double* T,
+                               int64_t ldt, int32_t precision, void* factors,
+                               size_t factor_bytes, void* work,
+                               size_t work_bytes, rad_stats* stats,
+                               void* stream);
+
 /* ---- absorbed heat fluxes ----------------------------------------------- */
 /*
  * Absorbed heat fluxes from REFs and direct heat fluxes (Sec. 4.2.3,

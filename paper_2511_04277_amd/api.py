@@ -134,6 +134,48 @@ def absorbed_flux(B: torch.Tensor, eps: torch.Tensor, rho: torch.Tensor, area: t
     return out[:, 0] if (vec and out.dim() == 2) else out
 
 
+SIGMA = 5.670374419e-8  # Stefan-Boltzmann constant, W m^-2 K^-4
+
+
+def steady_temperature(Y: torch.Tensor, weight: torch.Tensor, Q: torch.Tensor,
+                       t_fixed: Optional[torch.Tensor] = None, t_space: float = 3.0, sigma: float = SIGMA,
+                       precision: str = "fp64", factors: Optional["Factors"] = None,
+                       out: Optional[torch.Tensor] = None, want_stats: bool = True):
+    """Radiation-only steady node temperatures (eq. 3.12-3.14, GR = sigma w Y, eq. 4.2).
+
+    Y: n x (n+1) REFs (face or node level); weight: eps A per node; Q: heat
+    input in W, n values or n x m load cases; t_fixed: n values, > 0 holds a
+    node at that temperature, 0 leaves it free.  Returns (T, factors, stats)
+    with T shaped like Q.
+    """
+    n = Y.shape[0]
+    ldy = _mat(Y, "Y", n, n + 1)
+    _vec(weight, "weight", n)
+    _vec(t_fixed, "t_fixed", n)
+    vec = Q.dim() == 1
+    q = Q.unsqueeze(1) if vec else Q
+    m = q.shape[1]
+    ldq = _mat(q, "Q", n, m)
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float64, device=Y.device)
+    o = out.unsqueeze(1) if out.dim() == 1 else out
+    ldt = _mat(o, "T", n, m)
+    if factors is None or factors.n != n or factors.precision != precision:
+        factors = Factors(n, precision, Y.device)
+    lib = L.lib()
+    p = _PREC[precision]
+    work = WORKSPACE.get(Y.device, "steady", lib.rad_steady_temperature_workspace_bytes(n, p))
+    st = L.RadStats()
+    code = lib.rad_steady_temperature(_vp(Y), n, ldy, _vp(weight), _vp(q), m, ldq,
+                                      _vp(t_fixed), float(t_space), float(sigma),
+                                      _vp(o), ldt, p, _vp(factors.buf), factors.buf.numel(), _vp(work),
+                                      work.numel(), ctypes.byref(st) if want_stats else None, _stream(Y.device))
+    L.check(code, "rad_steady_temperature")
+    stats = st.as_dict() if want_stats else {}
+    stats["status"] = code
+    return (out[:, 0] if (vec and out.dim() == 2) else out), factors, stats
+
+
 class Factors:
     """Device buffer holding a factorization of K (reused by the adjoint)."""
 

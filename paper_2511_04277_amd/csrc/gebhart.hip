@@ -717,6 +717,66 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
   return RAD_OK;
 }
 
+extern "C" size_t rad_steady_temperature_workspace_bytes(int64_t n, int32_t precision) {
+  if (n < 1 || n > (1 << 20) || (precision != RAD_PREC_FP64 && precision != RAD_PREC_FP64_I8)) return 0;
+  return rad_gebhart_workspace_bytes(n, precision);
+}
+
+extern "C" int32_t rad_steady_temperature(const double* Y, int64_t n, int64_t ldy, const double* weight,
+                                          const double* Q, int64_t m, int64_t ldq, const double* t_fixed,
+                                          double t_space, double sigma, double* T, int64_t ldt,
+                                          int32_t precision, void* factors, size_t fbytes, void* work,
+                                          size_t wbytes, rad_stats* stats, void* stream) {
+  clear_error();
+  RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_steady_temperature: n out of range");
+  RAD_REQUIRE(m >= 1 && m <= RAD_STEADY_MAX_CASES, RAD_EINVAL,
+              "rad_steady_temperature: m outside [1, RAD_STEADY_MAX_CASES]");
+  RAD_REQUIRE(ldy >= n + 1 && ldq >= m && ldt >= m, RAD_EINVAL, "rad_steady_temperature: leading dimension too small");
+  RAD_REQUIRE(Y && weight && Q && T && factors, RAD_EINVAL, "rad_steady_temperature: NULL pointer");
+  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP64_I8, RAD_EINVAL,
+              "rad_steady_temperature: precision must be RAD_PREC_FP64 or RAD_PREC_FP64_I8");
+  RAD_REQUIRE(t_space >= 0.0 && t_space <= 1.0e75 && sigma > 0.0 && sigma <= 1.0e300, RAD_EINVAL,
+              "rad_steady_temperature: t_space or sigma out of range");
+  RAD_REQUIRE(fbytes >= factor_bytes(n, precision) && reinterpret_cast<uintptr_t>(factors) % 256 == 0,
+              RAD_EWORKSPACE, "rad_steady_temperature: factor buffer too small or not 256-byte aligned");
+  GebWork w = geb_work(work, wbytes, n, precision, false);
+  RAD_REQUIRE(w.ok && reinterpret_cast<uintptr_t>(work) % 256 == 0, RAD_EWORKSPACE,
+              "rad_steady_temperature: workspace too small or not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = static_cast<int>(n), mi = static_cast<int>(m);
+  // the right-hand sides occupy one full 64-column tile (zero past m)
+  constexpr int SS_RHS = 64;
+  static_assert(SS_RHS >= RAD_STEADY_MAX_CASES, "right-hand side tile narrower than the case limit");
+  const EmuWork* ew = precision == RAD_PREC_FP64_I8 ? &w.emu : nullptr;
+  Fact<double> f = make_fact<double>(factors, factor_layout<double>(n));
+  double* X = static_cast<double*>(w.y);
+  const double xs = (t_space * t_space) * (t_space * t_space);
+  hipLaunchKernelGGL(scalars_init, dim3(1), dim3(64), 0, s, w.sc);
+  hipLaunchKernelGGL(ss_form, dim3(f.np), dim3(256), 0, s, Y, static_cast<long>(ldy), ni, weight, Q,
+                     static_cast<long>(ldq), mi, t_fixed, xs, sigma, f.kf, f.ldk, f.np, X, w.ldy, w.sc);
+  RAD_HIP_CHECK(factor_forward<double>(f, X, w.ldy, SS_RHS, w.sc, s, ew, static_cast<double*>(w.scr)));
+  RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
+  RAD_HIP_CHECK(back_solve<double>(f, X, w.ldy, SS_RHS, static_cast<double*>(w.scr), w.ldy, s, ew));
+  hipLaunchKernelGGL(ss_output, dim3(static_cast<unsigned>(ceil_div(n * m, 256))), dim3(256), 0, s, X, w.ldy, ni,
+                     mi, t_fixed, T, static_cast<long>(ldt), w.sc);
+  RAD_HIP_CHECK(hipGetLastError());
+  if (!stats) return RAD_OK;
+  Scalars h{};
+  int rc = read_scalars(w.sc, &h, s);
+  if (rc != RAD_OK) return rc;
+  *stats = rad_stats{};
+  stats->device_status = h.status;
+  stats->converged = 1;
+  if (h.status < 0) {
+    set_error(h.status == RAD_ESINGULAR
+                  ? "rad_steady_temperature: singular balance (a free node without a path to space or a fixed node)"
+                  : "rad_steady_temperature: input out of range or non-finite, or no real temperature balances "
+                    "the heat input");
+    return h.status;
+  }
+  return RAD_OK;
+}
+
 namespace {
 // REF check workspace: closure maxima per 4-row block, reciprocity maxima per tile pair
 size_t ref_check_bytes(int64_t n) {

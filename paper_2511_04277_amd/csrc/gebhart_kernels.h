@@ -148,6 +148,89 @@ geb_form(const double* __restrict__ F, long ldf, int n, const double* __restrict
   if (bad) raise_status(&sc->status, RAD_ENONFINITE);
 }
 
+// Radiation-only steady balance (eq. 3.12-3.14 with GR_ij = sigma w_i Y_ij,
+// eq. 4.2) in x = T^4, each free row divided by sigma w_i:
+//   free i:  (s_i - Y_ii) x_i - sum_{j != i} Y_ij x_j = Q_i / (sigma w_i) + Y_i,space x_space,
+//            s_i = sum_{j <= n} Y_ij (the row sum, space included);
+//   fixed i: x_i = T_i^4.
+// One workgroup per row of the padded matrix; rows past n are identity rows.
+__global__ void __launch_bounds__(256)
+ss_form(const double* __restrict__ Y, long ldy, int n, const double* __restrict__ w,
+        const double* __restrict__ Q, long ldq, int m, const double* __restrict__ tfix, double xs, double sigma,
+        double* __restrict__ KF, long ldk, int np, double* __restrict__ R, long ldr, Scalars* sc) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  const bool real = i < n;
+  const double t = (real && tfix) ? tfix[i] : 0.0;
+  const bool fixed = t > 0.0;
+  const bool row = real && !fixed;
+  const double* yrow = Y + static_cast<long>(i) * ldy;
+  int bad = 0;
+  double s = 0.0;
+  if (row)
+    for (long j = threadIdx.x; j <= n; j += blockDim.x) {
+      const double v = yrow[j];
+      bad |= !(v >= 0.0 && v <= 1.0e300);
+      s += v;
+    }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  s = (red[0] + red[1]) + (red[2] + red[3]);
+  const double wi = real ? w[i] : 1.0;
+  if (threadIdx.x == 0 && real) {
+    bad |= !(wi > 0.0 && wi <= 1.0e300);
+    bad |= !(t >= 0.0 && t <= 1.0e300);
+  }
+  double* krow = KF + static_cast<long>(i) * ldk;
+  for (long j = threadIdx.x; j < ldk; j += blockDim.x) {
+    double kv = (i == j) ? 1.0 : 0.0;
+    if (row && j < n) {
+      const double v = yrow[j];
+      kv = (i == j) ? s - v : -v;
+    }
+    krow[j] = j < np ? kv : 0.0;
+  }
+  double* rrow = R + static_cast<long>(i) * ldr;
+  const double ysp = row ? yrow[n] : 0.0;
+  for (long c = threadIdx.x; c < ldr; c += blockDim.x) {
+    double rv = 0.0;
+    if (real && c < m) {
+      if (fixed) {
+        rv = (t * t) * (t * t);
+      } else {
+        const double qv = Q[static_cast<long>(i) * ldq + c];
+        bad |= !(qv >= -1.0e300 && qv <= 1.0e300);
+        rv = qv / (sigma * wi) + ysp * xs;
+      }
+    }
+    rrow[c] = rv;
+  }
+  if (bad) raise_status(&sc->status, RAD_ENONFINITE);
+}
+
+// T = x^(1/4) for free nodes (x <= 0: no real temperature balances the
+// given heat input, reported as RAD_ENONFINITE), the prescribed T otherwise.
+__global__ void __launch_bounds__(256)
+ss_output(const double* __restrict__ X, long ldx, int n, int m, const double* __restrict__ tfix,
+          double* __restrict__ T, long ldt, Scalars* sc) {
+  const long q = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= static_cast<long>(n) * m) return;
+  const int i = static_cast<int>(q / m), c = static_cast<int>(q % m);
+  const double tf = tfix ? tfix[i] : 0.0;
+  double out = tf;
+  if (!(tf > 0.0)) {
+    const double x = X[static_cast<long>(i) * ldx + c];
+    if (x > 0.0 && x <= 1.0e300) {
+      out = sqrt(sqrt(x));
+    } else {
+      out = __builtin_nan("");
+      raise_status(&sc->status, RAD_ENONFINITE);
+    }
+  }
+  T[static_cast<long>(i) * ldt + c] = out;
+}
+
 // P = F_sq diag(rho) in FP64, zero outside n x n (refinement residuals).
 __global__ void __launch_bounds__(256)
 form_p64(const double* __restrict__ F, long ldf, int n, const double* __restrict__ rho,
