@@ -20,6 +20,8 @@ implements:
                   (Sec. 4.2.3, eq. 4.6).
 * ``steady``    - radiation-only steady-state node temperatures (Sec. 3.4.4,
                   eq. 3.12-3.14 with GR from REFs, eq. 4.2).
+* ``twosided``  - two-sided multi-node relations: node factors, view
+                  fractions and node emissivity (eq. 5.17, 5.29, C.4).
 
 All arithmetic is float64.  Functions whose result has a plain definition use
 that definition directly (a LAPACK solve, dense products, sums); the iterative
@@ -31,9 +33,10 @@ from .adjoint import gebhart_ref_adjoint
 from .aggregate import aggregate_nodes
 from .ahf import absorbed_flux
 from .steady import steady_temperature
+from .twosided import node_emissivity, node_view_factors, view_fractions
 
 __all__ = [
     "closure_step", "enforce_vf", "reciprocity_step", "kappa_fracvar", "mae",
     "form_k_e", "gebhart_ref", "ref_closure_residual", "ref_reciprocity_residual",
-    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux", "steady_temperature",
+    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux", "steady_temperature", "node_emissivity", "node_view_factors", "view_fractions",
 ]
