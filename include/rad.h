@@ -202,6 +202,43 @@ int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                             double* group_weight, void* work, size_t work_bytes,
                             rad_stats* stats, void* stream);
 
+/* ---- two-sided nodes ---------------------------------------------------- */
+/*
+ * A node is a sub-surface with C_n faces (one, A, or two, A and B); the
+ * face-level matrices below have one row per face, group[a] in [0, g) names
+ * the node of face a (device int32), column nf is deep space.  Node view
+ * factors and REFs of two-sided nodes (eq. 5.17 / 5.28) are
+ * rad_aggregate_nodes with the face areas as weights (W_G = C_n S_n, the
+ * node area of eq. 5.36) for view factors and eps_a S_a for REFs.
+ *
+ * rad_view_fractions: view fractions (Sec. 5.2.5, eq. 5.27 / 5.29), the
+ *   share of each face pair in its node pair's total,
+ *   R[a][b] = F[a][b] / sum_{a' in G(a), b' in G(b)} F[a'][b'] (b = nf:
+ *   deep space, summed over the faces of G(a)); 0 where that total is 0.
+ *   F, R: nf x (nf+1) (ld ldf, ldr >= nf+1).
+ * rad_node_emissivity: the emissivity of node G towards node H (App. C,
+ *   eq. C.4) that makes GR_GH = eps_GH C_G S_G B_GH with the node REF of
+ *   eq. 5.17: eps_GH = sum_{a in G} eps_a S_a sum_{b in H} B_ab /
+ *   sum_{a in G} S_a sum_{b in H} B_ab; where the denominator is 0, the
+ *   node's area-mean emissivity.  B: nf x (nf+1) face REFs (ld ldb); eps,
+ *   area: nf face values (eps in [0, 1], area > 0); E: g x (g+1) (ld lde).
+ * Every group must be non-empty and every id in range, eps and area in
+ * range; these are checked on the device and reported (RAD_EINVAL,
+ * RAD_ENONFINITE) when ``stats`` is non-NULL (which synchronises the stream).
+ * work: >= the matching *_workspace_bytes(nf, g), 256-byte aligned.
+ */
+size_t rad_view_fractions_workspace_bytes(int64_t nf, int64_t g);
+int32_t rad_view_fractions(const double* F, int64_t nf, int64_t ldf,
+                           const int32_t* group, int64_t g, double* R,
+                           int64_t ldr, void* work, size_t work_bytes,
+                           rad_stats* stats, void* stream);
+size_t rad_node_emissivity_workspace_bytes(int64_t nf, int64_t g);
+int32_t rad_node_emissivity(const double* B, int64_t nf, int64_t ldb,
+                            const double* eps, const double* area,
+                            const int32_t* group, int64_t g, double* E,
+                            int64_t lde, void* work, size_t work_bytes,
+                            rad_stats* stats, void* stream);
+
 /* ---- steady-state node temperatures ------------------------------------ */
 /*
  * Radiation-only steady state of the node heat equation (Sec. 3.4.4,

@@ -6,7 +6,7 @@ an operation needs the built library and a ROCm device.
 """
 from . import _lib
 from .api import (Batch, Factors, GebhartREF, absorbed_flux, aggregate_nodes, enforce_vf_, gebhart_ref,
-                  gebhart_ref_adjoint, ref_check, steady_temperature)
+                  gebhart_ref_adjoint, node_emissivity, ref_check, steady_temperature, view_fractions)
 
 __all__ = ["Batch", "Factors", "GebhartREF", "absorbed_flux", "aggregate_nodes", "enforce_vf_", "gebhart_ref",
-           "gebhart_ref_adjoint", "ref_check", "steady_temperature", "_lib"]
+           "gebhart_ref_adjoint", "node_emissivity", "ref_check", "steady_temperature", "view_fractions", "_lib"]

@@ -112,6 +112,10 @@ SIGNATURES = {
     "rad_gebhart_ref_adjoint": (_I32, [_P, _SZ, _I32, _P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P,
                                       _I64, _D, _I32, _P, _SZ, _STATS, _P]),
     "rad_aggregate_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_view_fractions_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_view_fractions": (_I32, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _SZ, _STATS, _P]),
+    "rad_node_emissivity_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_node_emissivity": (_I32, [_P, _I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _SZ, _STATS, _P]),
     "rad_steady_temperature_workspace_bytes": (_SZ, [_I64, _I32]),
     "rad_steady_temperature": (_I32, [_P, _I64, _I64, _P, _P, _I64, _I64, _P, _D, _D, _P, _I64, _I32, _P, _SZ,
                                       _P, _SZ, _STATS, _P]),

@@ -134,6 +134,44 @@ def absorbed_flux(B: torch.Tensor, eps: torch.Tensor, rho: torch.Tensor, area: t
     return out[:, 0] if (vec and out.dim() == 2) else out
 
 
+def view_fractions(F: torch.Tensor, group: torch.Tensor, g: int, out: Optional[torch.Tensor] = None,
+                   validate: bool = True) -> torch.Tensor:
+    """View fractions of two-sided nodes (eq. 5.29): each face pair's share of its node pair's total."""
+    nf = F.shape[0]
+    ldf = _mat(F, "F", nf, nf + 1)
+    _vec(group, "group", nf, torch.int32)
+    if out is None:
+        out = torch.empty((nf, nf + 1), dtype=torch.float64, device=F.device)
+    ldr = _mat(out, "R", nf, nf + 1)
+    lib = L.lib()
+    work = WORKSPACE.get(F.device, "vfrac", lib.rad_view_fractions_workspace_bytes(nf, g))
+    st = L.RadStats()
+    code = lib.rad_view_fractions(_vp(F), nf, ldf, _vp(group), g, _vp(out), ldr, _vp(work), work.numel(),
+                                  ctypes.byref(st) if validate else None, _stream(F.device))
+    L.check(code, "rad_view_fractions")
+    return out
+
+
+def node_emissivity(B: torch.Tensor, eps: torch.Tensor, area: torch.Tensor, group: torch.Tensor, g: int,
+                    out: Optional[torch.Tensor] = None, validate: bool = True) -> torch.Tensor:
+    """Pair-dependent emissivity of two-sided nodes (App. C, eq. C.4), g x (g+1)."""
+    nf = B.shape[0]
+    ldb = _mat(B, "B", nf, nf + 1)
+    _vec(eps, "eps", nf)
+    _vec(area, "area", nf)
+    _vec(group, "group", nf, torch.int32)
+    if out is None:
+        out = torch.empty((g, g + 1), dtype=torch.float64, device=B.device)
+    lde = _mat(out, "E", g, g + 1)
+    lib = L.lib()
+    work = WORKSPACE.get(B.device, "nodeeps", lib.rad_node_emissivity_workspace_bytes(nf, g))
+    st = L.RadStats()
+    code = lib.rad_node_emissivity(_vp(B), nf, ldb, _vp(eps), _vp(area), _vp(group), g, _vp(out), lde, _vp(work),
+                                   work.numel(), ctypes.byref(st) if validate else None, _stream(B.device))
+    L.check(code, "rad_node_emissivity")
+    return out
+
+
 SIGMA = 5.670374419e-8  # Stefan-Boltzmann constant, W m^-2 K^-4
 
 

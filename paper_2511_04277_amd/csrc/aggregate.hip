@@ -105,7 +105,7 @@ csr_scatter(const int* __restrict__ group, int n, int g, const int* __restrict__
 __global__ void __launch_bounds__(AGG_THREADS)
 agg_reduce(const double* __restrict__ X, long ldx, int n, const double* __restrict__ w,
            const int* __restrict__ offs, const int* __restrict__ members, int g,
-           double* __restrict__ Y, long ldy, double* __restrict__ gw) {
+           double* __restrict__ Y, long ldy, double* __restrict__ gw, int divide) {
   const int G = blockIdx.y;
   const int H = blockIdx.x * AGG_THREADS + threadIdx.x;  // output column (g == space)
   const int rb = offs[G], re = offs[G + 1];
@@ -128,7 +128,7 @@ agg_reduce(const double* __restrict__ X, long ldx, int n, const double* __restri
       acc += w[i] * s;
     }
   }
-  Y[static_cast<long>(G) * ldy + H] = acc / wsum;
+  Y[static_cast<long>(G) * ldy + H] = divide ? acc / wsum : acc;
   if (gw && H == 0) gw[G] = wsum;
 }
 
@@ -161,6 +161,111 @@ AggLayout agg_layout(void* work, size_t bytes, int64_t n, int64_t g) {
   l.bytes = cv.used;
   l.ok = cv.ok;
   return l;
+}
+
+// Two-sided nodes (eq. 5.29): the share of face pair (a, b) in the sum over
+// the face pairs of its node pair, D_GH = sum_{a' in G, b' in H} F_a'b'.
+// Group ids outside [0, g) (reported by the CSR build) write 0 and read nothing.
+__global__ void __launch_bounds__(256)
+vf_fraction(const double* __restrict__ F, long ldf, int nf, const int* __restrict__ group, int g,
+            const double* __restrict__ D, long ldd, double* __restrict__ R, long ldr) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b > nf) return;
+  const int H = b < nf ? group[b] : g;
+  for (int a = blockIdx.y; a < nf; a += gridDim.y) {
+    const int G = group[a];
+    double out = 0.0;
+    if (G >= 0 && G < g && H >= 0 && H <= g) {
+      const double den = D[static_cast<long>(G) * ldd + H];
+      if (den != 0.0) out = F[static_cast<long>(a) * ldf + b] / den;
+    }
+    R[static_cast<long>(a) * ldr + b] = out;
+  }
+}
+
+// eq. C.4: eps_GH = (sum_{a in G} eps_a S_a sum_{b in H} B_ab) / (sum_{a in G} S_a sum_{b in H} B_ab);
+// a pair without exchange gets the node's area-mean emissivity.
+__global__ void __launch_bounds__(256)
+ne_ratio(const double* __restrict__ num, const double* __restrict__ den, long ldd, const double* __restrict__ we,
+         const double* __restrict__ ws, int g, double* __restrict__ E, long lde) {
+  const int H = blockIdx.x * 256 + threadIdx.x;
+  if (H > g) return;
+  for (int G = blockIdx.y; G < g; G += gridDim.y) {
+    const double d = den[static_cast<long>(G) * ldd + H];
+    E[static_cast<long>(G) * lde + H] = d != 0.0 ? num[static_cast<long>(G) * ldd + H] / d : we[G] / ws[G];
+  }
+}
+
+// eps_a S_a per face, with the range checks of the optical inputs
+__global__ void __launch_bounds__(256)
+face_weights(const double* __restrict__ eps, const double* __restrict__ area, int n, double* __restrict__ out,
+             int* __restrict__ status) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= n) return;
+  const double e = eps[a], s = area[a];
+  if (!(e >= 0.0 && e <= 1.0 && s > 0.0 && s <= 1.0e300)) atomicMin(status, RAD_ENONFINITE);
+  out[a] = e * s;
+}
+
+__global__ void __launch_bounds__(256) fill_ones(double* __restrict__ p, int n) {
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a < n) p[a] = 1.0;
+}
+
+// CSR of the group map (members of each group in face order), shared by the reductions of one call
+void agg_build(const int32_t* group, int n, int g, const AggLayout& l, hipStream_t s) {
+  const long ncnt = static_cast<long>(l.nch) * g;
+  hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, s, l.status, 1L);
+  hipLaunchKernelGGL(zero_ints, dim3(static_cast<unsigned>(std::min<long>(ceil_div(ncnt, 256), 4096))), dim3(256), 0,
+                     s, l.cnt, ncnt);
+  hipLaunchKernelGGL(csr_rank, dim3(static_cast<unsigned>(l.nch)), dim3(CSR_CHUNK), 0, s, group, n, g, l.rank,
+                     l.cnt, l.status);
+  hipLaunchKernelGGL(csr_offsets, dim3(1), dim3(1024), 0, s, l.cnt, l.nch, g, l.offs, l.status);
+  hipLaunchKernelGGL(csr_scatter, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, group, n, g,
+                     l.rank, l.cnt, l.offs, l.members);
+}
+
+void agg_sums(const double* X, long ldx, int n, const double* w, const AggLayout& l, int g, double* Y, long ldy,
+              double* gw, hipStream_t s) {
+  dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
+  ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
+  hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, ldx, n, w, l.offs, l.members, g, Y, ldy, gw, 0);
+}
+
+int read_status(const int* dev, hipStream_t s, int* out) {
+  if (hipMemcpyAsync(out, dev, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return RAD_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return RAD_EHIP;
+  return RAD_OK;
+}
+
+struct TwoSidedLayout {
+  AggLayout agg;
+  double* w;     // per-face weights (ones, or eps S)
+  double* d0;    // g x (g+1) pair sums
+  double* d1;    // g x (g+1) pair sums (emissivity denominator)
+  double* gw0;   // g group weights
+  double* gw1;
+  long ldd;
+  size_t bytes;
+  bool ok;
+};
+
+TwoSidedLayout two_sided_layout(void* work, size_t bytes, int64_t nf, int64_t g, bool emissivity) {
+  TwoSidedLayout t{};
+  t.agg = agg_layout(work, bytes, nf, g);
+  const size_t off = align_up(t.agg.bytes, 256);
+  Carve cv(work && bytes > off ? static_cast<char*>(work) + off : nullptr, bytes > off ? bytes - off : 0);
+  t.ldd = g + 1;
+  t.w = cv.take<double>(static_cast<size_t>(nf));
+  t.d0 = cv.take<double>(static_cast<size_t>(g) * t.ldd);
+  if (emissivity) {
+    t.d1 = cv.take<double>(static_cast<size_t>(g) * t.ldd);
+    t.gw0 = cv.take<double>(static_cast<size_t>(g));
+    t.gw1 = cv.take<double>(static_cast<size_t>(g));
+  }
+  t.bytes = off + cv.used;
+  t.ok = t.agg.ok && cv.ok;
+  return t;
 }
 
 }  // namespace
@@ -203,7 +308,7 @@ extern "C" int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
     ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
     hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, static_cast<long>(ldx),
                        static_cast<int>(n), weight, l.offs, l.members, static_cast<int>(g), Y,
-                       static_cast<long>(ldy), group_weight);
+                       static_cast<long>(ldy), group_weight, 1);
   }
   RAD_HIP_CHECK(hipGetLastError());
   if (!stats) return RAD_OK;
@@ -214,6 +319,90 @@ extern "C" int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
   stats->device_status = st;
   if (st < 0) {
     set_error("rad_aggregate_nodes: empty group or group id out of [0, g)");
+    return st;
+  }
+  return RAD_OK;
+}
+
+extern "C" size_t rad_view_fractions_workspace_bytes(int64_t nf, int64_t g) {
+  if (nf < 1 || g < 1) return 0;
+  return two_sided_layout(nullptr, 0, nf, g, false).bytes;
+}
+
+extern "C" int32_t rad_view_fractions(const double* F, int64_t nf, int64_t ldf, const int32_t* group, int64_t g,
+                                      double* R, int64_t ldr, void* work, size_t work_bytes, rad_stats* stats,
+                                      void* stream) {
+  clear_error();
+  RAD_REQUIRE(nf >= 1 && nf <= (1 << 24), RAD_EINVAL, "rad_view_fractions: nf out of range");
+  RAD_REQUIRE(g >= 1 && g <= nf, RAD_EINVAL, "rad_view_fractions: g must be in [1, nf]");
+  RAD_REQUIRE(ldf >= nf + 1 && ldr >= nf + 1, RAD_EINVAL, "rad_view_fractions: ld too small");
+  RAD_REQUIRE(F && group && R, RAD_EINVAL, "rad_view_fractions: NULL pointer");
+  RAD_REQUIRE(ceil_div(nf, CSR_CHUNK) * g <= (int64_t(1) << 31) - 1, RAD_EINVAL,
+              "rad_view_fractions: too many groups for this nf");
+  TwoSidedLayout t = two_sided_layout(work, work_bytes, nf, g, false);
+  RAD_REQUIRE(t.ok && reinterpret_cast<uintptr_t>(work) % 256 == 0, RAD_EWORKSPACE,
+              "rad_view_fractions: workspace too small or not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = static_cast<int>(nf), gi = static_cast<int>(g);
+  agg_build(group, ni, gi, t.agg, s);
+  hipLaunchKernelGGL(fill_ones, dim3(static_cast<unsigned>(ceil_div(nf, 256))), dim3(256), 0, s, t.w, ni);
+  agg_sums(F, static_cast<long>(ldf), ni, t.w, t.agg, gi, t.d0, t.ldd, nullptr, s);
+  hipLaunchKernelGGL(vf_fraction, dim3(static_cast<unsigned>(ceil_div(nf + 1, 256)),
+                                       static_cast<unsigned>(std::min<int64_t>(nf, 32768))),
+                     dim3(256), 0, s, F, static_cast<long>(ldf), ni, group, gi, t.d0, t.ldd, R,
+                     static_cast<long>(ldr));
+  RAD_HIP_CHECK(hipGetLastError());
+  if (!stats) return RAD_OK;
+  int st = 0;
+  int rc = read_status(t.agg.status, s, &st);
+  if (rc != RAD_OK) return rc;
+  *stats = rad_stats{};
+  stats->device_status = st;
+  if (st < 0) {
+    set_error("rad_view_fractions: empty group or group id out of [0, g)");
+    return st;
+  }
+  return RAD_OK;
+}
+
+extern "C" size_t rad_node_emissivity_workspace_bytes(int64_t nf, int64_t g) {
+  if (nf < 1 || g < 1) return 0;
+  return two_sided_layout(nullptr, 0, nf, g, true).bytes;
+}
+
+extern "C" int32_t rad_node_emissivity(const double* B, int64_t nf, int64_t ldb, const double* eps,
+                                       const double* area, const int32_t* group, int64_t g, double* E,
+                                       int64_t lde, void* work, size_t work_bytes, rad_stats* stats,
+                                       void* stream) {
+  clear_error();
+  RAD_REQUIRE(nf >= 1 && nf <= (1 << 24), RAD_EINVAL, "rad_node_emissivity: nf out of range");
+  RAD_REQUIRE(g >= 1 && g <= nf, RAD_EINVAL, "rad_node_emissivity: g must be in [1, nf]");
+  RAD_REQUIRE(ldb >= nf + 1 && lde >= g + 1, RAD_EINVAL, "rad_node_emissivity: ld too small");
+  RAD_REQUIRE(B && eps && area && group && E, RAD_EINVAL, "rad_node_emissivity: NULL pointer");
+  RAD_REQUIRE(ceil_div(nf, CSR_CHUNK) * g <= (int64_t(1) << 31) - 1, RAD_EINVAL,
+              "rad_node_emissivity: too many groups for this nf");
+  TwoSidedLayout t = two_sided_layout(work, work_bytes, nf, g, true);
+  RAD_REQUIRE(t.ok && reinterpret_cast<uintptr_t>(work) % 256 == 0, RAD_EWORKSPACE,
+              "rad_node_emissivity: workspace too small or not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = static_cast<int>(nf), gi = static_cast<int>(g);
+  agg_build(group, ni, gi, t.agg, s);
+  hipLaunchKernelGGL(face_weights, dim3(static_cast<unsigned>(ceil_div(nf, 256))), dim3(256), 0, s, eps, area, ni,
+                     t.w, t.agg.status);
+  agg_sums(B, static_cast<long>(ldb), ni, t.w, t.agg, gi, t.d0, t.ldd, t.gw0, s);
+  agg_sums(B, static_cast<long>(ldb), ni, area, t.agg, gi, t.d1, t.ldd, t.gw1, s);
+  hipLaunchKernelGGL(ne_ratio, dim3(static_cast<unsigned>(ceil_div(g + 1, 256)), static_cast<unsigned>(std::min<int64_t>(g, 32768))), dim3(256),
+                     0, s, t.d0, t.d1, t.ldd, t.gw0, t.gw1, gi, E, static_cast<long>(lde));
+  RAD_HIP_CHECK(hipGetLastError());
+  if (!stats) return RAD_OK;
+  int st = 0;
+  int rc = read_status(t.agg.status, s, &st);
+  if (rc != RAD_OK) return rc;
+  *stats = rad_stats{};
+  stats->device_status = st;
+  if (st < 0) {
+    set_error(st == RAD_ENONFINITE ? "rad_node_emissivity: eps outside [0, 1] or area not > 0"
+                                   : "rad_node_emissivity: empty group or group id out of [0, g)");
     return st;
   }
   return RAD_OK;
