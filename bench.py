@@ -343,6 +343,9 @@ def main() -> int:
         0.0, 1400.0, (n, AHF_CASES)), d)
     log(f"steady temperatures ({AHF_CASES} cases, {prec}): {steady['ms']:.2f} ms, "
         f"{steady['tflops_fp64_equivalent']:.1f} TFLOP/s FP64-equivalent")
+    two = two_sided_timing(rad, F0, slots[0]["B"], eps, area, d)
+    log(f"two-sided nodes ({n} faces -> {n // 2}): view fractions {two['view_fractions_ms']:.3f} ms "
+        f"({two['view_fractions_gbs']:.0f} GB/s), node emissivity {two['node_emissivity_ms']:.3f} ms")
 
     # ---- CPU baseline: the oracle on a bounded sample of the same step ----
     if not args.no_cpu_baseline:
@@ -396,9 +399,49 @@ def main() -> int:
         "ref_residuals": {"closure": float(chk_h[0]), "reciprocity": float(chk_h[1])},
         "absorbed_flux": ahf,
         "steady_temperature": steady,
+        "two_sided_nodes": two,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def two_sided_timing(rad, F, B, eps, area, d, reps: int = 5) -> dict:
+    """View fractions (eq. 5.29) and node emissivity (eq. C.4) with the faces
+    paired into two-sided nodes (a fixed random pairing), outside the step.
+    Algorithmic bytes: the view fractions read F twice (pair sums, then the
+    quotients) and write R once, 24 n (n+1); the emissivity reads B twice."""
+    import numpy as np
+    import torch
+    from synth import workloads as W
+    n = F.shape[0]
+    perm = W.rng_for(8192, 3).permutation(n)
+    grp = np.empty(n, dtype=np.int32)
+    grp[perm[0::2]] = np.arange(n // 2)
+    grp[perm[1::2]] = np.arange(n // 2)
+    g = n // 2
+    group = d(grp, torch.int32)
+    R = torch.empty_like(F)
+    E = torch.empty((g, g + 1), dtype=torch.float64, device=F.device)
+    rad.view_fractions(F, group, g, out=R)
+    rad.node_emissivity(B, eps, area, group, g, out=E)
+    torch.cuda.synchronize()
+    res = {"faces": n, "nodes": g}
+    for name, fn, nbytes in (("view_fractions", lambda: rad.view_fractions(F, group, g, out=R, validate=False),
+                              24.0 * n * (n + 1)),
+                             ("node_emissivity", lambda: rad.node_emissivity(B, eps, area, group, g, out=E,
+                                                                             validate=False),
+                              16.0 * n * (n + 1))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{name}_ms"] = ms
+        res[f"{name}_gbs"] = nbytes / (ms * 1e-3) / 1e9
+        res[f"{name}_hbm_frac"] = res[f"{name}_gbs"] / PEAK_HBM_GBS
+    return res
 
 
 def steady_timing(rad, B, eps, rho, area, w, prec, qd_host, d, reps: int = 3) -> dict:
