@@ -22,6 +22,8 @@ implements:
                   eq. 3.12-3.14 with GR from REFs, eq. 4.2).
 * ``twosided``  - two-sided multi-node relations: node factors, view
                   fractions and node emissivity (eq. 5.17, 5.29, C.4).
+* ``lsq``       - least-squares optimum closure + reciprocity enforcer with
+                  NNR and SPVA (Sec. 3.5.5, eq. 3.41-3.52; App. A).
 
 All arithmetic is float64.  Functions whose result has a plain definition use
 that definition directly (a LAPACK solve, dense products, sums); the iterative
@@ -34,9 +36,10 @@ from .aggregate import aggregate_nodes
 from .ahf import absorbed_flux
 from .steady import steady_temperature
 from .twosided import node_emissivity, node_view_factors, view_fractions
+from .lsq import enforce_lsq
 
 __all__ = [
     "closure_step", "enforce_vf", "reciprocity_step", "kappa_fracvar", "mae",
     "form_k_e", "gebhart_ref", "ref_closure_residual", "ref_reciprocity_residual",
-    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux", "steady_temperature", "node_emissivity", "node_view_factors", "view_fractions",
+    "gebhart_ref_adjoint", "aggregate_nodes", "absorbed_flux", "steady_temperature", "node_emissivity", "node_view_factors", "view_fractions", "enforce_lsq",
 ]
