@@ -26,8 +26,9 @@ the restrictions are written on F as above (the same affine set).  Eq. 3.41
 gives A N(N-1) columns; the unknowns and eq. 3.42 need N (N+1).  NNR
 removes the negative coefficients' columns, as SPVA does (a reciprocity row
 with one partner removed stays and holds the other at zero, which keeps
-reciprocity).  Each round projects the MCRT input restricted to the
-coefficients still active.
+reciprocity; that partner is then exactly zero, which is set explicitly so
+that a rounding-level negative cannot trigger NNR).  Each round projects the
+MCRT input restricted to the coefficients still active.
 """
 from __future__ import annotations
 
@@ -82,6 +83,13 @@ def enforce_lsq(f: np.ndarray, omega: np.ndarray, nnr: bool = True, spva: bool =
         rounds += 1
         xh = np.zeros_like(x)
         xh[active] = _project(a[:, active], b, x[active])
+        # an entry whose reciprocal partner is held at zero is zero by its
+        # reciprocity row (Omega_i F_ik = 0): set it exactly, so that rounding
+        # of the projection cannot decide the NNR test
+        am = active.reshape(n, n + 1)
+        lone = am[:, :n] & ~am[:, :n].T
+        np.fill_diagonal(lone, False)
+        xh.reshape(n, n + 1)[:, :n][lone] = 0.0
         neg = active & (xh < 0.0)
         if not nnr or not neg.any() or rounds >= max_rounds:
             break
