@@ -202,6 +202,36 @@ int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                             double* group_weight, void* work, size_t work_bytes,
                             rad_stats* stats, void* stream);
 
+/* ---- least-squares optimum enforcer ------------------------------------- */
+/*
+ * Closure + reciprocity enforcement by the least-squares optimum for open
+ * systems (Sec. 3.5.5, eq. 3.41-3.52): the view factors closest to F (in the
+ * Euclidean norm over all n (n+1) entries) whose rows sum to one and with
+ * omega_i F_ik = omega_k F_ki.  Flags: RAD_LSQ_NNR repeats the projection
+ * with the negative entries held at zero until none is negative (App. A.1);
+ * RAD_LSQ_SPVA holds the zero entries of F at zero from the start
+ * (App. A.2).  The projection is solved through the n x n system of the
+ * closure multipliers (the reciprocity multipliers eliminated in closed
+ * form), factored by the Gebhart solve's block LDU, one solve per round.
+ * F: n x (n+1) input, 1 <= n <= 65535 (ld ldf, not modified); omega: n
+ * weights (the areas);
+ * Fout: n x (n+1) result (ld ldo), a different buffer; max_rounds >= 1.
+ * precision: RAD_PREC_FP64 or RAD_PREC_FP64_I8.  factors: >=
+ * rad_gebhart_factor_bytes(n, precision); work: >=
+ * rad_enforce_lsq_workspace_bytes(n, precision); both 256-byte aligned.
+ * Synchronises the stream once per round (the NNR test).  stats (nullable):
+ * iters = rounds run.  Returns RAD_WNOTCONVERGED if negative entries remain
+ * after max_rounds; RAD_ENONFINITE for a non-finite input.
+ */
+#define RAD_LSQ_NNR 1
+#define RAD_LSQ_SPVA 2
+size_t rad_enforce_lsq_workspace_bytes(int64_t n, int32_t precision);
+int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf,
+                        const double* omega, double* Fout, int64_t ldo,
+                        int32_t flags, int32_t max_rounds, int32_t precision,
+                        void* factors, size_t factor_bytes, void* work,
+                        size_t work_bytes, rad_stats* stats, void* stream);
+
 /* ---- two-sided nodes ---------------------------------------------------- */
 /*
  * A node is a sub-surface with C_n faces (one, A, or two, A and B); the

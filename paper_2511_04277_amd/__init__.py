@@ -5,8 +5,8 @@ this package is its Python binding.  Importing it does not need a GPU; calling
 an operation needs the built library and a ROCm device.
 """
 from . import _lib
-from .api import (Batch, Factors, GebhartREF, absorbed_flux, aggregate_nodes, enforce_vf_, gebhart_ref,
+from .api import (Batch, Factors, GebhartREF, absorbed_flux, aggregate_nodes, enforce_lsq, enforce_vf_, gebhart_ref,
                   gebhart_ref_adjoint, node_emissivity, ref_check, steady_temperature, view_fractions)
 
-__all__ = ["Batch", "Factors", "GebhartREF", "absorbed_flux", "aggregate_nodes", "enforce_vf_", "gebhart_ref",
+__all__ = ["Batch", "Factors", "GebhartREF", "absorbed_flux", "aggregate_nodes", "enforce_lsq", "enforce_vf_", "gebhart_ref",
            "gebhart_ref_adjoint", "node_emissivity", "ref_check", "steady_temperature", "view_fractions", "_lib"]

@@ -26,6 +26,8 @@ RAD_KAPPA_HALF = 1
 RAD_PREC_FP64 = 0
 RAD_PREC_FP32_IR = 1
 RAD_PREC_FP64_I8 = 2
+RAD_LSQ_NNR = 1
+RAD_LSQ_SPVA = 2
 
 
 class RadStats(ctypes.Structure):
@@ -112,6 +114,8 @@ SIGNATURES = {
     "rad_gebhart_ref_adjoint": (_I32, [_P, _SZ, _I32, _P, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P,
                                       _I64, _D, _I32, _P, _SZ, _STATS, _P]),
     "rad_aggregate_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rad_enforce_lsq_workspace_bytes": (_SZ, [_I64, _I32]),
+    "rad_enforce_lsq": (_I32, [_P, _I64, _I64, _P, _P, _I64, _I32, _I32, _I32, _P, _SZ, _P, _SZ, _STATS, _P]),
     "rad_view_fractions_workspace_bytes": (_SZ, [_I64, _I64]),
     "rad_view_fractions": (_I32, [_P, _I64, _I64, _P, _I64, _P, _I64, _P, _SZ, _STATS, _P]),
     "rad_node_emissivity_workspace_bytes": (_SZ, [_I64, _I64]),

@@ -134,6 +134,32 @@ def absorbed_flux(B: torch.Tensor, eps: torch.Tensor, rho: torch.Tensor, area: t
     return out[:, 0] if (vec and out.dim() == 2) else out
 
 
+def enforce_lsq(F: torch.Tensor, area: torch.Tensor, nnr: bool = True, spva: bool = True, max_rounds: int = 50,
+                precision: str = "fp64", factors: Optional["Factors"] = None, out: Optional[torch.Tensor] = None):
+    """Least-squares optimum closure + reciprocity enforcement (eq. 3.41-3.52) with
+    NNR / SPVA (App. A).  Returns (F_hat, factors, stats); F is not modified."""
+    n = F.shape[0]
+    ldf = _mat(F, "F", n, n + 1)
+    _vec(area, "area", n)
+    if out is None:
+        out = torch.empty((n, n + 1), dtype=torch.float64, device=F.device)
+    ldo = _mat(out, "Fout", n, n + 1)
+    if factors is None or factors.n != n or factors.precision != precision:
+        factors = Factors(n, precision, F.device)
+    lib = L.lib()
+    p = _PREC[precision]
+    work = WORKSPACE.get(F.device, "lsq", lib.rad_enforce_lsq_workspace_bytes(n, p))
+    st = L.RadStats()
+    flags = (L.RAD_LSQ_NNR if nnr else 0) | (L.RAD_LSQ_SPVA if spva else 0)
+    code = lib.rad_enforce_lsq(_vp(F), n, ldf, _vp(area), _vp(out), ldo, flags, int(max_rounds), p,
+                               _vp(factors.buf), factors.buf.numel(), _vp(work), work.numel(), ctypes.byref(st),
+                               _stream(F.device))
+    L.check(code, "rad_enforce_lsq")
+    stats = st.as_dict()
+    stats["status"] = code
+    return out, factors, stats
+
+
 def view_fractions(F: torch.Tensor, group: torch.Tensor, g: int, out: Optional[torch.Tensor] = None,
                    validate: bool = True) -> torch.Tensor:
     """View fractions of two-sided nodes (eq. 5.29): each face pair's share of its node pair's total."""

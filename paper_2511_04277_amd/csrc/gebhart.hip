@@ -778,6 +778,98 @@ extern "C" int32_t rad_steady_temperature(const double* Y, int64_t n, int64_t ld
 }
 
 namespace {
+struct LsqWork {
+  GebWork geb;
+  uint8_t* mask[2];
+  int* negatives;
+  size_t bytes;
+  bool ok;
+};
+
+LsqWork lsq_work(void* work, size_t bytes, int64_t n, int32_t prec) {
+  LsqWork l{};
+  const size_t gb = align_up(geb_work(nullptr, 0, n, prec, false).bytes, 256);
+  l.geb = geb_work(work, std::min(bytes, gb), n, prec, false);
+  Carve cv(work && bytes > gb ? static_cast<char*>(work) + gb : nullptr, bytes > gb ? bytes - gb : 0);
+  const size_t mb = static_cast<size_t>(n) * static_cast<size_t>(n + 1);
+  l.mask[0] = cv.take<uint8_t>(mb);
+  l.mask[1] = cv.take<uint8_t>(mb);
+  l.negatives = cv.take<int>(64);
+  l.bytes = gb + cv.used;
+  l.ok = l.geb.ok && cv.ok;
+  return l;
+}
+}  // namespace
+
+extern "C" size_t rad_enforce_lsq_workspace_bytes(int64_t n, int32_t precision) {
+  if (n < 1 || n > (1 << 20) || (precision != RAD_PREC_FP64 && precision != RAD_PREC_FP64_I8)) return 0;
+  return lsq_work(nullptr, 0, n, precision).bytes;
+}
+
+extern "C" int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf, const double* omega, double* Fout,
+                                   int64_t ldo, int32_t flags, int32_t max_rounds, int32_t precision,
+                                   void* factors, size_t fbytes, void* work, size_t wbytes, rad_stats* stats,
+                                   void* stream) {
+  clear_error();
+  RAD_REQUIRE(n >= 1 && n <= 65535, RAD_EINVAL, "rad_enforce_lsq: n out of range (1..65535)");
+  RAD_REQUIRE(ldf >= n + 1 && ldo >= n + 1, RAD_EINVAL, "rad_enforce_lsq: ldf or ldo < n+1");
+  RAD_REQUIRE(F && omega && Fout && factors, RAD_EINVAL, "rad_enforce_lsq: NULL pointer");
+  RAD_REQUIRE(F != Fout, RAD_EINVAL, "rad_enforce_lsq: F and Fout must not be the same buffer");
+  RAD_REQUIRE((flags & ~(RAD_LSQ_NNR | RAD_LSQ_SPVA)) == 0 && max_rounds >= 1, RAD_EINVAL,
+              "rad_enforce_lsq: unknown flag or max_rounds < 1");
+  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP64_I8, RAD_EINVAL,
+              "rad_enforce_lsq: precision must be RAD_PREC_FP64 or RAD_PREC_FP64_I8");
+  RAD_REQUIRE(fbytes >= factor_bytes(n, precision) && reinterpret_cast<uintptr_t>(factors) % 256 == 0,
+              RAD_EWORKSPACE, "rad_enforce_lsq: factor buffer too small or not 256-byte aligned");
+  LsqWork l = lsq_work(work, wbytes, n, precision);
+  RAD_REQUIRE(l.ok && reinterpret_cast<uintptr_t>(work) % 256 == 0, RAD_EWORKSPACE,
+              "rad_enforce_lsq: workspace too small or not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ni = static_cast<int>(n);
+  const int nnr = (flags & RAD_LSQ_NNR) != 0;
+  constexpr int LSQ_RHS = 64;
+  const GebWork& w = l.geb;
+  const EmuWork* ew = precision == RAD_PREC_FP64_I8 ? &w.emu : nullptr;
+  Fact<double> f = make_fact<double>(factors, factor_layout<double>(n));
+  double* Y = static_cast<double*>(w.y);
+  const dim3 egrid(static_cast<unsigned>(ceil_div(n + 1, 256)), static_cast<unsigned>(n));
+  hipLaunchKernelGGL(scalars_init, dim3(1), dim3(64), 0, s, w.sc);
+  hipLaunchKernelGGL(lsq_mask_init, egrid, dim3(256), 0, s, F, static_cast<long>(ldf), ni,
+                     (flags & RAD_LSQ_SPVA) ? 1 : 0, l.mask[0], w.sc);
+  int rounds = 0, negatives = 0, cur = 0;
+  Scalars h{};
+  for (;;) {
+    ++rounds;
+    hipLaunchKernelGGL(fill_zero<int>, dim3(1), dim3(64), 0, s, l.negatives, 1L);
+    hipLaunchKernelGGL(lsq_schur, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, omega, l.mask[cur],
+                       f.kf, f.ldk, f.np, Y, w.ldy);
+    RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, LSQ_RHS, w.sc, s, ew, static_cast<double*>(w.scr)));
+    RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
+    RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, LSQ_RHS, static_cast<double*>(w.scr), w.ldy, s, ew));
+    hipLaunchKernelGGL(lsq_update, egrid, dim3(256), 0, s, F, static_cast<long>(ldf), ni, omega, l.mask[cur], Y,
+                       w.ldy, nnr, l.mask[1 - cur], Fout, static_cast<long>(ldo), l.negatives);
+    RAD_HIP_CHECK(hipGetLastError());
+    RAD_HIP_CHECK(hipMemcpyAsync(&negatives, l.negatives, sizeof(int), hipMemcpyDeviceToHost, s));
+    int rc = read_scalars(w.sc, &h, s);  // synchronises the stream
+    if (rc != RAD_OK) return rc;
+    cur = 1 - cur;
+    if (h.status < 0 || !nnr || negatives == 0 || rounds >= max_rounds) break;
+  }
+  if (stats) {
+    *stats = rad_stats{};
+    stats->iters = rounds;
+    stats->device_status = h.status;
+    stats->converged = h.status >= 0 && (!nnr || negatives == 0);
+  }
+  if (h.status < 0) {
+    set_error(h.status == RAD_ESINGULAR ? "rad_enforce_lsq: singular closure system"
+                                        : "rad_enforce_lsq: non-finite view factor");
+    return h.status;
+  }
+  return (nnr && negatives > 0) ? RAD_WNOTCONVERGED : RAD_OK;
+}
+
+namespace {
 // REF check workspace: closure maxima per 4-row block, reciprocity maxima per tile pair
 size_t ref_check_bytes(int64_t n) {
   const int64_t t = ceil_div(n, 64);

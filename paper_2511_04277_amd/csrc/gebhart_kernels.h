@@ -231,6 +231,130 @@ ss_output(const double* __restrict__ X, long ldx, int n, int m, const double* __
   T[static_cast<long>(i) * ldt + c] = out;
 }
 
+// ---- least-squares optimum enforcer (eq. 3.41-3.52 with NNR / SPVA) ------
+// The projection of F onto {closure rows sum to 1, W_i F_ik = W_k F_ki} over
+// the active entries (a_ik = 1) is F_hat = F - A^T y with (A A^T) y = A F - b.
+// A A^T has a diagonal closure block (n_i = active entries of row i), a
+// diagonal reciprocity block (d_ik = W_i^2 a_ik + W_k^2 a_ki per pair) and a
+// coupling with two entries per pair, so eliminating the pair multipliers
+// leaves an n x n system for the closure multipliers lambda:
+//   S_ii = n_i - sum_{k != i} a_ik W_i^2 / d_ik,  S_ik = a_ik a_ki W_i W_k / d_ik,
+//   S lambda = (sum_j a_ij F_ij - 1) - sum_{k != i} a_ik W_i rho_ik / d_ik,
+//   rho_ik = W_i a_ik F_ik - W_k a_ki F_ki;
+// then F_hat_ik = F_ik - lambda_i - W_i nu_ik with the pair multiplier
+//   nu_ik = (rho_ik - a_ik W_i lambda_i + a_ki W_k lambda_k) / d_ik
+// (k != i, k < n), and F_hat_ik = F_ik - lambda_i on the diagonal and the
+// space column.  A row with no active entry gets lambda_i = 0.
+
+// mask (n x (n+1), ld n+1): 1 = active; SPVA drops the zeros of the input
+__global__ void __launch_bounds__(256)
+lsq_mask_init(const double* __restrict__ F, long ldf, int n, int spva, uint8_t* __restrict__ mask,
+              Scalars* sc) {
+  const int i = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k > n) return;
+  const double v = F[static_cast<long>(i) * ldf + k];
+  if (!(v >= -1.0e300 && v <= 1.0e300)) raise_status(&sc->status, RAD_ENONFINITE);
+  mask[static_cast<long>(i) * (n + 1) + k] = (spva && v == 0.0) ? 0 : 1;
+}
+
+__global__ void __launch_bounds__(256)
+lsq_schur(const double* __restrict__ F, long ldf, int n, const double* __restrict__ W,
+          const uint8_t* __restrict__ mask, double* __restrict__ KF, long ldk, int np,
+          double* __restrict__ Y, long ldy) {
+  __shared__ double red[4][4];
+  const int i = blockIdx.x;
+  const long ldm = n + 1;
+  double* krow = KF + static_cast<long>(i) * ldk;
+  double cnt = 0.0, rsum = 0.0, sub = 0.0, t = 0.0;
+  if (i < n) {
+    const double wi = W[i];
+    const double* frow = F + static_cast<long>(i) * ldf;
+    const uint8_t* mrow = mask + static_cast<long>(i) * ldm;
+    for (int k = threadIdx.x; k <= n; k += blockDim.x) {
+      const int aik = mrow[k];
+      const double fik = frow[k];
+      cnt += aik;
+      rsum += aik ? fik : 0.0;
+      double sik = 0.0;
+      if (k < n && k != i) {
+        const int aki = mask[static_cast<long>(k) * ldm + i];
+        const double wk = W[k];
+        const double d = wi * wi * aik + wk * wk * aki;
+        if (d > 0.0) {
+          const double fki = F[static_cast<long>(k) * ldf + i];
+          const double rho = (aik ? wi * fik : 0.0) - (aki ? wk * fki : 0.0);
+          if (aik) {
+            sub += wi * wi / d;
+            t += wi * rho / d;
+          }
+          if (aik && aki) sik = wi * wk / d;
+        }
+      }
+      if (k < n) krow[k] = sik;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_xor(cnt, off);
+    rsum += __shfl_xor(rsum, off);
+    sub += __shfl_xor(sub, off);
+    t += __shfl_xor(t, off);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[wv][0] = cnt;
+    red[wv][1] = rsum;
+    red[wv][2] = sub;
+    red[wv][3] = t;
+  }
+  // padding columns (and the whole row past n): identity
+  for (long k = (i < n ? n : 0) + threadIdx.x; k < ldk; k += blockDim.x) krow[k] = (k == i && k < np) ? 1.0 : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0 && i < n) {
+    const double c = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    const double r = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    const double sb = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
+    const double tt = (red[0][3] + red[1][3]) + (red[2][3] + red[3][3]);
+    krow[i] = c > 0.0 ? c - sb : 1.0;
+    Y[static_cast<long>(i) * ldy] = c > 0.0 ? (r - 1.0) - tt : 0.0;
+  }
+  double* yrow = Y + static_cast<long>(i) * ldy;
+  for (long c = (i < n ? 1 : 0) + threadIdx.x; c < ldy; c += blockDim.x) yrow[c] = 0.0;
+}
+
+// F_hat from lambda (column 0 of Y); NNR: negative active entries leave the
+// next round's mask; every entry of the mask is written (ping-pong buffers).
+__global__ void __launch_bounds__(256)
+lsq_update(const double* __restrict__ F, long ldf, int n, const double* __restrict__ W,
+           const uint8_t* __restrict__ mask, const double* __restrict__ Y, long ldy, int nnr,
+           uint8_t* __restrict__ mask_next, double* __restrict__ Fo, long ldo, int* __restrict__ negatives) {
+  const int i = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k > n) return;
+  const long ldm = n + 1;
+  const int aik = mask[static_cast<long>(i) * ldm + k];
+  double v = 0.0;
+  if (aik) {
+    const double li = Y[static_cast<long>(i) * ldy];
+    const double fik = F[static_cast<long>(i) * ldf + k];
+    v = fik - li;
+    if (k < n && k != i) {
+      const int aki = mask[static_cast<long>(k) * ldm + i];
+      const double wi = W[i], wk = W[k];
+      const double d = wi * wi + wk * wk * aki;
+      const double fki = aki ? F[static_cast<long>(k) * ldf + i] : 0.0;
+      const double lk = Y[static_cast<long>(k) * ldy];
+      const double nu = ((wi * fik - wk * fki) - wi * li + (aki ? wk * lk : 0.0)) / d;
+      // a partner held at zero makes the pair's row read W_i F_ik = 0: exactly zero
+      v = aki ? v - wi * nu : 0.0;
+    }
+  }
+  const int neg = nnr && aik && v < 0.0;
+  if (neg) atomicAdd(negatives, 1);
+  mask_next[static_cast<long>(i) * ldm + k] = aik && !neg;
+  Fo[static_cast<long>(i) * ldo + k] = v;
+}
+
 // P = F_sq diag(rho) in FP64, zero outside n x n (refinement residuals).
 __global__ void __launch_bounds__(256)
 form_p64(const double* __restrict__ F, long ldf, int n, const double* __restrict__ rho,
