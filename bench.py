@@ -344,6 +344,9 @@ def main() -> int:
     log(f"steady temperatures ({AHF_CASES} cases, {prec}): {steady['ms']:.2f} ms, "
         f"{steady['tflops_fp64_equivalent']:.1f} TFLOP/s FP64-equivalent")
     two = two_sided_timing(rad, F0, slots[0]["B"], eps, area, d)
+    lsq = lsq_timing(rad, F0, area)
+    log(f"least-squares enforcer (NNR + SPVA): " + ", ".join(
+        f"{p} {v['ms']:.1f} ms / {v['rounds']} rounds" for p, v in lsq.items()))
     log(f"two-sided nodes ({n} faces -> {n // 2}): view fractions {two['view_fractions_ms']:.3f} ms "
         f"({two['view_fractions_gbs']:.0f} GB/s), node emissivity {two['node_emissivity_ms']:.3f} ms")
 
@@ -400,9 +403,32 @@ def main() -> int:
         "absorbed_flux": ahf,
         "steady_temperature": steady,
         "two_sided_nodes": two,
+        "lsq_enforcer": lsq,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def lsq_timing(rad, F, area, reps: int = 3) -> dict:
+    """Least-squares optimum enforcer with NNR and SPVA (eq. 3.41-3.52, App. A)
+    on the noisy input, outside the step, in both solve precisions.  Each
+    round is one n x n solve (2/3 n^3 flops) plus O(n^2) passes."""
+    import numpy as np
+    import torch
+    res = {}
+    for prec in ("fp64", "fp64_i8"):
+        out, fac, st = rad.enforce_lsq(F, area, precision=prec)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out, fac, st = rad.enforce_lsq(F, area, precision=prec, factors=fac, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        res[prec] = {"ms": float(np.median(times)), "rounds": int(st["iters"]), "converged": int(st["converged"])}
+    return res
 
 
 def two_sided_timing(rad, F, B, eps, area, d, reps: int = 5) -> dict:
