@@ -53,11 +53,13 @@ __device__ __forceinline__ char* uniform_ptr(const double* p) {
   const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
   return reinterpret_cast<char*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
+// F streams through once per sweep (it is larger than the last-level cache
+// at the sizes that matter), so its loads and stores are nontemporal.
 __device__ __forceinline__ double row_ld(const double* row, unsigned col) {
-  return *reinterpret_cast<const double*>(uniform_ptr(row) + col * 8u);
+  return __builtin_nontemporal_load(reinterpret_cast<const double*>(uniform_ptr(row) + col * 8u));
 }
 __device__ __forceinline__ void row_st(double* row, unsigned col, double v) {
-  *reinterpret_cast<double*>(uniform_ptr(row) + col * 8u) = v;
+  __builtin_nontemporal_store(v, reinterpret_cast<double*>(uniform_ptr(row) + col * 8u));
 }
 
 // kappa of eq. 3.25 from the pair (f_ij, f_ji) and c = A^2 / N of both faces:
