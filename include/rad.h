@@ -254,7 +254,8 @@ int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf,
  *   area: nf face values (eps in [0, 1], area > 0); E: g x (g+1) (ld lde).
  * Every group must be non-empty and every id in range, eps and area in
  * range; these are checked on the device and reported (RAD_EINVAL,
- * RAD_ENONFINITE) when ``stats`` is non-NULL (which synchronises the stream).
+ * RAD_ENONFINITE) when ``stats`` is non-NULL (which synchronises the stream);
+ * after such an error the output is unspecified.
  * work: >= the matching *_workspace_bytes(nf, g), 256-byte aligned.
  */
 size_t rad_view_fractions_workspace_bytes(int64_t nf, int64_t g);

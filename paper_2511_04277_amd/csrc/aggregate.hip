@@ -183,6 +183,32 @@ vf_fraction(const double* __restrict__ F, long ldf, int nf, const int* __restric
   }
 }
 
+// The same quotients with one workgroup per node G: its row of D is staged
+// in LDS once, then the rows of G's faces stream through (coalesced loads
+// and stores; the column-to-node map is read coalesced and stays in cache,
+// the gathers hit LDS).  Used when g + 1 doubles fit in VF_LDS_BYTES.
+constexpr size_t VF_LDS_BYTES = 64 * 1024;
+
+__global__ void __launch_bounds__(256)
+vf_fraction_lds(const double* __restrict__ F, long ldf, int nf, const int* __restrict__ group, int g,
+                const int* __restrict__ offs, const int* __restrict__ members, const double* __restrict__ D,
+                long ldd, double* __restrict__ R, long ldr) {
+  extern __shared__ double drow[];  // g + 1
+  const int G = blockIdx.x;
+  for (int h = threadIdx.x; h <= g; h += blockDim.x) drow[h] = D[static_cast<long>(G) * ldd + h];
+  __syncthreads();
+  for (int m = offs[G]; m < offs[G + 1]; ++m) {
+    const int a = members[m];
+    const double* frow = F + static_cast<long>(a) * ldf;
+    double* rrow = R + static_cast<long>(a) * ldr;
+    for (int b = threadIdx.x; b <= nf; b += blockDim.x) {
+      const int H = b < nf ? group[b] : g;
+      const double den = (H >= 0 && H <= g) ? drow[H] : 0.0;
+      rrow[b] = den != 0.0 ? __builtin_nontemporal_load(frow + b) / den : 0.0;
+    }
+  }
+}
+
 // eq. C.4: eps_GH = (sum_{a in G} eps_a S_a sum_{b in H} B_ab) / (sum_{a in G} S_a sum_{b in H} B_ab);
 // a pair without exchange gets the node's area-mean emissivity.
 __global__ void __launch_bounds__(256)
@@ -347,10 +373,18 @@ extern "C" int32_t rad_view_fractions(const double* F, int64_t nf, int64_t ldf, 
   agg_build(group, ni, gi, t.agg, s);
   hipLaunchKernelGGL(fill_ones, dim3(static_cast<unsigned>(ceil_div(nf, 256))), dim3(256), 0, s, t.w, ni);
   agg_sums(F, static_cast<long>(ldf), ni, t.w, t.agg, gi, t.d0, t.ldd, nullptr, s);
-  hipLaunchKernelGGL(vf_fraction, dim3(static_cast<unsigned>(ceil_div(nf + 1, 256)),
-                                       static_cast<unsigned>(std::min<int64_t>(nf, 32768))),
-                     dim3(256), 0, s, F, static_cast<long>(ldf), ni, group, gi, t.d0, t.ldd, R,
-                     static_cast<long>(ldr));
+  const size_t lds = static_cast<size_t>(g + 1) * sizeof(double);
+  if (lds <= VF_LDS_BYTES) {
+    // (rows of faces whose node id is out of range are left unwritten; the
+    // call reports that error when stats are requested)
+    hipLaunchKernelGGL(vf_fraction_lds, dim3(static_cast<unsigned>(g)), dim3(256), lds, s, F, static_cast<long>(ldf),
+                       ni, group, gi, t.agg.offs, t.agg.members, t.d0, t.ldd, R, static_cast<long>(ldr));
+  } else {
+    hipLaunchKernelGGL(vf_fraction, dim3(static_cast<unsigned>(ceil_div(nf + 1, 256)),
+                                         static_cast<unsigned>(std::min<int64_t>(nf, 32768))),
+                       dim3(256), 0, s, F, static_cast<long>(ldf), ni, group, gi, t.d0, t.ldd, R,
+                       static_cast<long>(ldr));
+  }
   RAD_HIP_CHECK(hipGetLastError());
   if (!stats) return RAD_OK;
   int st = 0;
