@@ -58,6 +58,8 @@ TRAFFIC = {
                                 [os.path.join(_CSRC, "gemm.h")]),
     "emu_gemm<7>": (os.path.join(ROOT, "profiles", "emu_gemm_open_box_n8192_traffic.txt"),
                     [os.path.join(_CSRC, "emu_kernels.h")]),
+    "ahf_partial<16, 2, 4, true>": (os.path.join(ROOT, "profiles", "ahf_partial_open_box_n8192_traffic.txt"),
+                                    [os.path.join(_CSRC, "ahf.hip")]),
 }
 
 
@@ -525,7 +527,8 @@ def absorbed_flux_timing(rad, L, lib, B, eps, rho, area, qd, reps: int = 20) -> 
     gbs = p.bytes / p.launches / k_s / 1e9
     return {"n": n, "load_cases": m, "ms": e0.elapsed_time(e1) / reps, "kernel": "ahf_partial<16, 2, 4, true>",
             "kernel_us": 1e6 * k_s, "algorithmic_bytes_per_launch": p.bytes / p.launches, "gbs": gbs,
-            "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm"}
+            "hbm_frac": gbs / PEAK_HBM_GBS, "bound": "hbm",
+            "traffic": measured_traffic("ahf_partial<16, 2, 4, true>", "fp64")}
 
 
 def run_batch64(args) -> int:
