@@ -15,7 +15,11 @@ solve is also timed alone in FP64, in FP64 with int8 digit products and in
 FP32 + FP64 refinement, each checked against the FP64 CPU oracle on the same
 enforced F (max |dB| must be <= 1e-10); the step uses the fastest variant
 that meets that bound.  After the timed steps, the absorbed heat fluxes of
-eq. 4.6 (16 load cases) are timed on the step's REFs, outside the step.
+eq. 4.6 (16 load cases) are timed on the step's REFs, outside the step, and
+so are the next rows (steady temperatures, two-sided nodes, least-squares
+enforcer).  The 16384-face open box is then enforced and solved in every
+precision, each B compared with the oracle on all of its entries
+(``target_n16384``), and the oracle is timed on the host (``cpu_baseline``).
 
 Prints one JSON line (see the keys at the end of main()).
 """
@@ -107,6 +111,8 @@ def main() -> int:
     ap.add_argument("--solve-variants", default="fp64,fp64_i8,fp32_ir1,fp32_ir",
                     help="comma list of Gebhart variants timed alone and checked against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the 16384-face leg (solves timed and checked against the oracle on every entry)")
     ap.add_argument("--inflight", type=int, default=2,
                     help="steps in flight on separate streams (1: one step after another)")
     ap.add_argument("--workload", choices=["headline", "batch64"], default="headline",
@@ -209,9 +215,7 @@ def main() -> int:
     # ---- oracle on the same enforced F: accuracy (and CPU baseline) -------
     cpu = None
     import oracle
-    t_orc = time.perf_counter()
     b_ref = oracle.gebhart_ref(F_enf_host, inst.eps[0], inst.rho[0])
-    t_orc_solve = time.perf_counter() - t_orc
     for name in solve:
         solve[name]["max_abs_err"] = float(np.abs(solve[name].pop("B") - b_ref).max())
         log(f"gebhart {name}: max|B - B_oracle| = {solve[name]['max_abs_err']:.3e}")
@@ -319,21 +323,30 @@ def main() -> int:
                           "tflops": (p.flops / (p.total_ms * 1e-3) / 1e12) if p.flops else None,
                           "gbs": (p.bytes / (p.total_ms * 1e-3) / 1e9) if p.bytes else None}
     pk = profs[L.PROFILE_KINDS.index(dom)]
+    # achieved = the method's flops (2 M N K of each FP64 product) per launch
+    # over the launch's average duration; the peak is that of the number type
+    # the kernel's matrix instructions execute in
     achieved = pk.flops / pk.launches / (pk.total_ms / pk.launches * 1e-3) / 1e12
     extra = {}
     if dom == "gemm_i8x":
-        # the kernel's own arithmetic: 28 int8 digit products per FP64 product
-        extra["fp64_equivalent_tflops"] = achieved
-        achieved *= I8X_PRODUCTS
-        peak, unit, kname = PEAK_TFLOPS["int8"], "TOP/s", "emu_gemm<7>"
+        peak, kname, executes = PEAK_TFLOPS["int8"], "emu_gemm<7>", "int8 MFMA (digit products)"
+        # the int8 work actually issued: 28 digit products per FP64 product
+        extra["int8_tops_issued"] = achieved * I8X_PRODUCTS
+        extra["mfma_issue_frac"] = achieved * I8X_PRODUCTS / PEAK_TFLOPS["int8"]
+        extra["fp64_equivalent_frac_of_fp64_peak"] = achieved / PEAK_TFLOPS["fp64"]
+    elif dom == "gemm_f64":
+        peak, kname, executes = PEAK_TFLOPS["fp64"], "gemm_lds<double, false>", "FP64 MFMA"
     else:
-        peak, unit = PEAK_TFLOPS["fp64" if dom == "gemm_f64" else "fp32"], "TFLOP/s"
-        kname = f"gemm_lds<{'double' if dom == 'gemm_f64' else 'float'}, false>"
-    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": unit, **extra,
-                "frac": achieved / peak, "traffic": measured_traffic(kname, prec),
+        peak, kname, executes = PEAK_TFLOPS["fp32"], "gemm_lds<float, false>", "FP32 MFMA"
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(kname, prec), "executes_in": executes,
+                **extra,
                 "algorithmic_bytes_per_launch": pk.bytes / pk.launches,
                 "flops_per_launch": pk.flops / pk.launches, "avg_launch_us": 1000.0 * pk.total_ms / pk.launches,
-                "launches_timed": int(pk.launches), "timed_launches_from": "the last timed step"}
+                "launches_timed": int(pk.launches), "timed_launches_from": "the last timed step",
+                # the whole LU + solves of the FP64 variant: algorithmic flops over time and the FP64 peak
+                "lu_mfma_frac": solve.get("fp64", {}).get("solve_frac_of_peak"),
+                "lu_mfma_frac_of": "FP64 solve alone (2/3 n^3 + 2 n^2 (n+1) flops / time / 78.6 TFLOP/s)"}
     sw = profs_all[L.PROFILE_KINDS.index("enforce_sweep")]
     if sw.launches:
         kern["enforce_sweep"]["hbm_frac"] = (sw.bytes / (sw.total_ms * 1e-3) / 1e9) / PEAK_HBM_GBS
@@ -352,31 +365,16 @@ def main() -> int:
     log(f"two-sided nodes ({n} faces -> {n // 2}): view fractions {two['view_fractions_ms']:.3f} ms "
         f"({two['view_fractions_gbs']:.0f} GB/s), node emissivity {two['node_emissivity_ms']:.3f} ms")
 
+    # ---- the spec size: 16384 faces, full-matrix parity --------------
+    target = None
+    if not args.no_target:
+        target = target_n16384(rad, oracle, W, d)
+
     # ---- CPU baseline: the oracle on a bounded sample of the same step ----
     if not args.no_cpu_baseline:
-        import threadpoolctl
-        threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
-        f_in = inst.f_noisy
-        k_iter = 1
-        t = time.perf_counter()
-        oracle.enforce_vf(f_in, inst.area, inst.n_rays, "fracvar", tol=0.0, max_iter=k_iter)
-        t_enf_iter = (time.perf_counter() - t) / k_iter
-        gnp = G.cpu().numpy()
-        t = time.perf_counter()
-        oracle.gebhart_ref_adjoint(F_enf_host, inst.eps[0], inst.rho[0], b_ref, gnp)
-        t_adj = time.perf_counter() - t
-        t = time.perf_counter()
-        y1h, w1h = oracle.aggregate_nodes(b_ref, inst.eps[0] * inst.area, g1, n1)
-        oracle.aggregate_nodes(y1h, w1h, g2, n2)
-        t_agg = time.perf_counter() - t
-        s_cpu = t_enf_iter * est["iters"] + t_orc_solve + t_adj + t_agg
-        cpu = {"value": 1.0 / s_cpu, "unit": "REF matrices/s", "cores": int(threads), "kind": "oracle",
-               "sample": (f"one step's parts on the n={n} input: {k_iter} of {est['iters']} enforcement "
-                          f"iterations timed and scaled ({t_enf_iter:.2f} s each), the REF solve "
-                          f"({t_orc_solve:.1f} s, LAPACK getrf/getrs), the adjoint ({t_adj:.1f} s) and the "
-                          f"two-level aggregation ({t_agg:.1f} s), each timed once"),
-               "seconds_per_step": s_cpu, "host_cpus": os.cpu_count()}
-        log(f"cpu baseline: {s_cpu:.1f} s per step on {threads} BLAS threads")
+        cpu = cpu_baseline_timing(oracle, inst, F_enf_host, b_ref, G.cpu().numpy(), est["iters"], n1, n2)
+        log(f"cpu baseline: {cpu['seconds_per_step']:.1f} s per step on {cpu['cores']} BLAS threads "
+            f"({cpu['cpu_model']}); one thread: {cpu['one_thread']['seconds_per_step']:.1f} s")
 
     out = {
         "metric": "REF matrices/sec at N=8192, mixed-prec vs FP64 LU at <=1e-10 err; LU MFMA %",
@@ -406,9 +404,178 @@ def main() -> int:
         "steady_temperature": steady,
         "two_sided_nodes": two,
         "lsq_enforcer": lsq,
+        "target_n16384": target,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_timing(oracle, inst, f_enf, b_ref, g_host, iters: int, n1: int, n2: int) -> dict:
+    """The oracle on the host cores, one part of the step at a time on the
+    8192-face input: each part run once as a warm-up (the solve's warm-up is
+    the accuracy check run just before), then the median of three timed runs
+    (time.perf_counter).  The step is 'iters' enforcement iterations, one
+    solve, one adjoint and the two-level aggregation; one enforcement
+    iteration is timed and multiplied by the iteration count of the GPU run
+    (the whole enforcement would take about 12 minutes).  A one-thread figure
+    for scale: the solve with BLAS limited to one thread, its factorization
+    timed whole and its triangular solves on 1024 of the n + 1 right-hand
+    sides scaled to all of them (their cost is linear in the count); the
+    enforcement and aggregation parts are single-threaded NumPy in both."""
+    import numpy as np
+    import scipy.linalg as sla
+    import threadpoolctl
+    threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
+    eps, rho, area = inst.eps[0], inst.rho[0], inst.area
+    g1, g2 = inst.groups
+
+    def med3(fn, warm=True):
+        if warm:
+            fn()
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), [float(x) for x in ts]
+
+    t_enf, r_enf = med3(lambda: oracle.enforce_vf(inst.f_noisy, area, inst.n_rays, "fracvar", tol=0.0, max_iter=1))
+    log(f"cpu baseline: enforcement iteration {t_enf:.2f} s")
+    t_sol, r_sol = med3(lambda: oracle.gebhart_ref(f_enf, eps, rho), warm=False)
+    log(f"cpu baseline: solve {t_sol:.2f} s")
+    t_adj, r_adj = med3(lambda: oracle.gebhart_ref_adjoint(f_enf, eps, rho, b_ref, g_host))
+    log(f"cpu baseline: adjoint {t_adj:.2f} s")
+
+    def agg():
+        y1, w1 = oracle.aggregate_nodes(b_ref, eps * area, g1, n1)
+        oracle.aggregate_nodes(y1, w1, g2, n2)
+
+    t_agg, r_agg = med3(agg)
+    s_cpu = t_enf * iters + t_sol + t_adj + t_agg
+    n = f_enf.shape[0]
+    cols = min(1024, n + 1)
+    with threadpoolctl.threadpool_limits(1):
+        k, e = oracle.form_k_e(f_enf, eps, rho)
+        t = time.perf_counter()
+        lu = sla.lu_factor(k)
+        t_f1 = time.perf_counter() - t
+        t = time.perf_counter()
+        sla.lu_solve(lu, e[:, :cols])
+        t_s1 = (time.perf_counter() - t) * (n + 1) / cols
+    del k, e, lu
+    s_one = s_cpu - t_sol + (t_f1 + t_s1)
+    log(f"cpu baseline: one-thread solve {t_f1 + t_s1:.1f} s")
+    return {"value": 1.0 / s_cpu, "unit": "REF matrices/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one step's parts on the n={n} input, each the median of 3 timed runs after a warm-up: "
+                       f"one of the {iters} enforcement iterations (scaled by {iters}), the REF solve "
+                       f"(LAPACK getrf/getrs), the adjoint and the two-level aggregation"),
+            "seconds_per_step": s_cpu, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+            "parts_s": {"enforce_iteration": t_enf, "enforce_iterations": iters, "solve": t_sol, "adjoint": t_adj,
+                        "aggregation": t_agg},
+            "runs_s": {"enforce_iteration": r_enf, "solve": r_sol, "adjoint": r_adj, "aggregation": r_agg},
+            "one_thread": {"value": 1.0 / s_one, "seconds_per_step": s_one, "solve_s": t_f1 + t_s1,
+                           "sample": (f"the solve with one BLAS thread: getrf timed once, getrs on {cols} of "
+                                      f"{n + 1} right-hand sides scaled by {n + 1}/{cols}; the other parts as above "
+                                      "(single-threaded NumPy)")}}
+
+
+def target_n16384(rad, oracle, W, d, reps: int = 3) -> dict:
+    """The 16384-face open box (1 x 1 x 0.75 m, 1/64 m cells, 1e4 rays per
+    face): enforcement on the GPU to a closure defect <= 1e-13, then the REF
+    solve in FP64, with int8 digit products, and in FP32 with one FP64
+    refinement step, each timed (median of reps) and compared over all
+    16384 x 16385 entries with the oracle's pivoted LU solve of the same
+    enforced F; REF closure / reciprocity residuals (eq. 4.3-4.4) of each B,
+    and the REF aggregation 16384 -> 4096 -> 256 of the FP64 B."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    inst = W.config5()
+    n = inst.n
+    g1, g2 = inst.groups
+    n1, n2 = int(g1.max()) + 1, int(g2.max()) + 1
+    log(f"target n={n}: generated in {time.time() - t0:.1f}s")
+    F0 = d(inst.f_noisy)
+    F = torch.empty_like(F0)
+    area, nrays, eps, rho = d(inst.area), d(inst.n_rays), d(inst.eps[0]), d(inst.rho[0])
+    F.copy_(F0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    est = rad.enforce_vf_(F, area, nrays, kappa="fracvar", tol=ENF_TOL, max_iter=ENF_MAX)
+    e1.record()
+    torch.cuda.synchronize()
+    enf_ms = e0.elapsed_time(e1)
+    del F0
+    f_host = F.cpu().numpy()
+    out = {"n": n, "workload": "open_box_n16384 (1x1x0.75 m, 1/64 m cells, 1e4 rays/face)",
+           "enforce_iters": est["iters"], "enforce_ms": enf_ms, "enforce_closure_defect": est["closure_defect"],
+           "enforce_recip_err": est["recip_err"], "solve": {}}
+    B = torch.empty((n, n + 1), dtype=torch.float64, device=F.device)
+    hosts = {}
+    scale = None
+    for name, (prec, ir_tol, ir_max) in (("fp64", ("fp64", 0.0, 0)), ("fp64_i8", ("fp64_i8", 0.0, 0)),
+                                         ("fp32_ir1", ("fp32_ir", 1.0, 1))):
+        _, fac, st = rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=ir_tol, ir_max=ir_max, out=B)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rad.gebhart_ref(F, eps, rho, precision=prec, ir_tol=ir_tol, ir_max=ir_max, out=B, factors=fac,
+                            want_stats=False)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        chk = rad.ref_check(B, eps, area).cpu().numpy()
+        if scale is None:
+            scale = float((inst.eps[0] * inst.area).max()) * float(torch.amax(B[:, :n]).item())
+        tf = solve_flops(n) / (ms * 1e-3) / 1e12
+        out["solve"][name] = {"precision": prec, "ir_max": ir_max, "ms": ms, "ref_per_s": 1000.0 / ms,
+                              "solve_tflops": tf, "frac_of_fp64_peak": tf / PEAK_TFLOPS["fp64"],
+                              "device_status": st["device_status"], "ref_closure": float(chk[0]),
+                              "ref_reciprocity_rel": float(chk[1]) / scale}
+        if name == "fp64":
+            y1, w1 = rad.aggregate_nodes(B, eps * area, d(g1, torch.int32), n1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            y1, w1 = rad.aggregate_nodes(B, eps * area, d(g1, torch.int32), n1, validate=False)
+            rad.aggregate_nodes(y1, w1, d(g2, torch.int32), n2, validate=False)
+            e1.record()
+            torch.cuda.synchronize()
+            out["aggregation_ms"] = e0.elapsed_time(e1)
+            out["aggregation"] = f"{n}->{n1}->{n2}"
+        hosts[name] = B.cpu().numpy()
+        del fac
+        torch.cuda.empty_cache()
+        log(f"target n={n} {name}: {ms:.1f} ms ({tf:.1f} TFLOP/s), closure {chk[0]:.2e}")
+    del B, F
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    b_ref = oracle.gebhart_ref(f_host, inst.eps[0], inst.rho[0])
+    out["oracle_solve_s"] = time.perf_counter() - t
+    for name, b in hosts.items():
+        err = float(np.abs(b - b_ref).max())
+        out["solve"][name]["max_abs_err"] = err
+        out["solve"][name]["within_1e-10"] = err <= ERR_BOUND
+        log(f"target n={n} {name}: max|B - B_oracle| over all entries = {err:.3e}")
+    sv = out["solve"]
+    out["fp64_i8_beats_fp64"] = bool(sv["fp64_i8"]["ms"] < sv["fp64"]["ms"] and sv["fp64_i8"]["within_1e-10"])
+    out["fp32_ir1_beats_fp64"] = bool(sv["fp32_ir1"]["ms"] < sv["fp64"]["ms"] and sv["fp32_ir1"]["within_1e-10"])
+    return out
 
 
 def lsq_timing(rad, F, area, reps: int = 3) -> dict:

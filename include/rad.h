@@ -169,6 +169,9 @@ int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const double* eps
  * Lambda (nullable, ld ldl) receives K^{-T} G when non-NULL.
  * In RAD_PREC_FP32_IR the transposed solve is refined in FP64 (residual
  * G - K^T Lambda) until max|delta| <= ir_tol or ir_max steps.
+ * Device checks: a non-finite entry of G, or of a refinement residual,
+ * raises RAD_ENONFINITE (reported when ``stats`` is non-NULL; the
+ * refinement stops at once).
  * work: >= rad_adjoint_workspace_bytes(n, precision).
  */
 size_t rad_adjoint_workspace_bytes(int64_t n, int32_t precision);

@@ -68,7 +68,8 @@ def _project(a: np.ndarray, b: np.ndarray, x: np.ndarray) -> np.ndarray:
 
 
 def enforce_lsq(f: np.ndarray, omega: np.ndarray, nnr: bool = True, spva: bool = False, max_rounds: int = 100):
-    """Returns (F_hat, info); info['rounds'] = least-squares solves run."""
+    """Returns (F_hat, info); info['rounds'] = least-squares solves run,
+    info['active'] = the coefficients left free (n x (n+1) bool)."""
     f = np.asarray(f, dtype=np.float64)
     n = f.shape[0]
     omega = np.asarray(omega, dtype=np.float64)
@@ -95,4 +96,5 @@ def enforce_lsq(f: np.ndarray, omega: np.ndarray, nnr: bool = True, spva: bool =
             break
         active &= ~neg
     xh[~active] = 0.0
-    return xh.reshape(n, n + 1), {"rounds": rounds, "removed": int((~active).sum())}
+    return xh.reshape(n, n + 1), {"rounds": rounds, "removed": int((~active).sum()),
+                                  "active": active.reshape(n, n + 1).copy()}

@@ -328,8 +328,10 @@ class GebhartREF(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, F, eps, rho, precision="fp64"):
+        # statistics requested: the call waits for its kernels and raises on a
+        # device-detected error (out-of-range eps / rho, non-finite F, singular K)
         B, factors, _ = gebhart_ref(F.detach(), eps.detach(), rho.detach(), precision=precision,
-                                    want_stats=False)
+                                    want_stats=True)
         ctx.factors = factors
         ctx.save_for_backward(F, rho, B)
         return B
@@ -338,7 +340,7 @@ class GebhartREF(torch.autograd.Function):
     def backward(ctx, G):
         F, rho, B = ctx.saved_tensors
         ge, gr, _, _ = gebhart_ref_adjoint(ctx.factors, F.detach(), rho.detach(), B,
-                                           G.contiguous(), want_stats=False)
+                                           G.contiguous(), want_stats=True)
         return None, ge, gr, None
 
 

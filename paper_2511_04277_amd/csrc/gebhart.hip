@@ -942,14 +942,16 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
     const EmuWork* ew = precision == RAD_PREC_FP64_I8 ? &w.emu : nullptr;
     Fact<double> f = make_fact<double>(const_cast<void*>(factors), factor_layout<double>(n));
     double* Y = static_cast<double*>(w.y);
-    hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
+    hipLaunchKernelGGL(load_rhs<double>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy,
+                       w.sc);
     RAD_HIP_CHECK(transposed_solve<double>(f, Y, w.ldy, ni + 1, static_cast<double*>(w.scr), w.ldy, s, ew));
     lam = Y;
     ldlam = w.ldy;
   } else {
     Fact<float> f = make_fact<float>(const_cast<void*>(factors), factor_layout<float>(n));
     float* Y = static_cast<float*>(w.y);
-    hipLaunchKernelGGL(load_rhs<float>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy);
+    hipLaunchKernelGGL(load_rhs<float>, dim3(f.np), dim3(256), 0, s, G, static_cast<long>(ldg), ni, Y, w.ldy,
+                       w.sc);
     RAD_HIP_CHECK(transposed_solve<float>(f, Y, w.ldy, ni + 1, static_cast<float*>(w.scr), w.ldy, s));
     zero<double>(w.x, static_cast<long>(f.np) * w.ldx, s);
     hipLaunchKernelGGL((copy_block<float, double>), dim3(ni), dim3(256), 0, s, Y, w.ldy, ni, w.x, w.ldx);
@@ -971,7 +973,7 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
       ++ir_steps;
       int rc = read_scalars(w.sc, &h, s);
       if (rc != RAD_OK) return rc;
-      if (h.max_d <= ir_tol) break;
+      if (h.status < 0 || h.max_d <= ir_tol) break;
     }
     lam = w.x;
     ldlam = w.ldx;
@@ -998,6 +1000,10 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
   stats->ir_correction = h.max_d;
   stats->ir_residual = h.max_r;
   stats->converged = (precision != RAD_PREC_FP32_IR) || (ir_steps > 0 && h.max_d <= ir_tol);
+  if (h.status < 0) {
+    set_error("rad_gebhart_ref_adjoint: non-finite entry of G or of the refinement residual");
+    return h.status;
+  }
   if (precision == RAD_PREC_FP32_IR && ir_max > 0 && !(h.max_d <= ir_tol)) return RAD_WNOTCONVERGED;
   return RAD_OK;
 }

@@ -750,11 +750,14 @@ residual_to_rhs(const double* __restrict__ R, long ldr, int n, float* __restrict
                 Scalars* sc) {
   const int i = blockIdx.x;
   double m = 0.0;
+  int bad = 0;
   for (int j = threadIdx.x; j <= n; j += blockDim.x) {
     double v = R[static_cast<long>(i) * ldr + j];
+    bad |= !(fabs(v) <= 1.0e300);
     m = fmax(m, fabs(v));
     Y[static_cast<long>(i) * ldy + j] = static_cast<float>(v);
   }
+  if (bad) raise_status(&sc->status, RAD_ENONFINITE);
   block_max(m, &sc->max_r);
 }
 
@@ -772,14 +775,23 @@ apply_correction(const float* __restrict__ Y, long ldy, int n, double* __restric
   block_max(m, &sc->max_d);
 }
 
-// Y (T, np rows x ldy, zero outside n x (n+1)) <- G (fp64)
+// Y (T, np rows x ldy, zero outside n x (n+1)) <- G (fp64); a non-finite
+// entry of G raises RAD_ENONFINITE
 template <class T>
 __global__ void __launch_bounds__(256)
-load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long ldy) {
+load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long ldy, Scalars* sc) {
   const int i = blockIdx.x;
   T* y = Y + static_cast<long>(i) * ldy;
-  for (long j = threadIdx.x; j < ldy; j += blockDim.x)
-    y[j] = (j <= n && i < n) ? static_cast<T>(G[static_cast<long>(i) * ldg + j]) : T(0);
+  int bad = 0;
+  for (long j = threadIdx.x; j < ldy; j += blockDim.x) {
+    double v = 0.0;
+    if (j <= n && i < n) {
+      v = G[static_cast<long>(i) * ldg + j];
+      bad |= !(fabs(v) <= 1.0e300);
+    }
+    y[j] = static_cast<T>(v);
+  }
+  if (bad) raise_status(&sc->status, RAD_ENONFINITE);
 }
 
 

@@ -120,3 +120,33 @@ def test_chimney_assembly_n4096_gradient():
             # (solve and sum rounding / 2h); the oracle comparison above is the tight check
             scale = np.abs(host(ge if which == "eps" else gr)).max()
             assert abs(fdv - ad) <= 1e-6 * abs(ad) + 2e-6 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "fp64_i8"])
+def test_non_finite_gradient_is_reported(precision):
+    """A NaN in dJ/dB is raised by the adjoint (RAD_ENONFINITE) in every
+    precision, also through the autograd Function's backward; an
+    out-of-range rho is raised by the Function's forward."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    from paper_2511_04277_amd._lib import RadError
+    inst = W.small_box(3, 1, seed=4)
+    n = inst.n
+    fd, ed, rd = dev(inst.f_noisy), dev(inst.eps[0]), dev(inst.rho[0])
+    print(f"[adjoint] non-finite G n={n} precision={precision}", flush=True)
+    bd, fac, _ = rad.gebhart_ref(fd, ed, rd, precision=precision, ir_tol=1e-13)
+    g = np.ones((n, n + 1))
+    g[1, 2] = np.nan
+    with pytest.raises(RadError) as e:
+        rad.gebhart_ref_adjoint(fac, fd, rd, bd, dev(g), ir_tol=1e-13)
+    assert e.value.code == -2
+    eps = ed.clone().requires_grad_(True)
+    rho = rd.clone().requires_grad_(True)
+    b = rad.GebhartREF.apply(fd, eps, rho, precision)
+    with pytest.raises(RadError):
+        (dev(g) * b).sum().backward()
+    bad = inst.rho[0].copy()
+    bad[0] = 1.5
+    with pytest.raises(RadError) as e:
+        rad.GebhartREF.apply(fd, ed, dev(bad).requires_grad_(True), precision)
+    assert e.value.code == -2

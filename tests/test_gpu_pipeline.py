@@ -24,7 +24,7 @@ def test_enforce_solve_fluxes_temperatures(precision):
     rng = np.random.default_rng(12)
     qd = rng.uniform(0.0, 1400.0, (n, 4))
     # oracle chain
-    f_o, _ = oracle.enforce_vf(inst.f_noisy, inst.area, inst.n_rays, "fracvar", tol=1e-13, max_iter=400)
+    f_o, info = oracle.enforce_vf(inst.f_noisy, inst.area, inst.n_rays, "fracvar", tol=1e-13, max_iter=400)
     b_o = oracle.gebhart_ref(f_o, eps, rho)
     qa_o = oracle.absorbed_flux(b_o, eps, rho, inst.area, qd)
     g1 = np.arange(n) // 4  # runs of four faces per node
@@ -45,6 +45,14 @@ def test_enforce_solve_fluxes_temperatures(precision):
     np.add.at(qn, g1, host(Qa))
     T, _, sst = rad.steady_temperature(Y, Wn, dev(qn), t_space=3.0, precision=precision)
     t = host(T)
-    assert st["iters"] > 0
+    # every intermediate, element by element: the enforced F (same stopping
+    # iteration), the REFs, the node REFs and their weights, the fluxes and
+    # the temperatures
+    tol_b = 1e-12 if precision == "fp64" else 1e-10
+    assert st["iters"] == info["iters"] and st["converged"] == 1
+    assert np.abs(host(F) - f_o).max() <= 1e-13
+    assert np.abs(host(B) - b_o).max() <= tol_b
+    assert np.abs(host(Y) - y_o).max() <= tol_b
+    assert np.abs(host(Wn) - w_o).max() <= 1e-15 * np.abs(w_o).max()
     assert np.abs(host(Qa) - qa_o).max() <= 1e-10 * np.abs(qa_o).max()
     assert np.abs(t - t_o).max() <= 1e-10 * t_o.max()

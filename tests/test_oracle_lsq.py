@@ -75,3 +75,30 @@ def test_exact_factors_are_a_fixed_point():
     f, info = enforce_lsq(inst.f_exact, inst.area, nnr=True, spva=True)
     assert info["rounds"] == 1
     assert np.abs(f - inst.f_exact).max() <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["e1", "box"])
+@pytest.mark.parametrize("spva", [False, True])
+def test_nnr_spva_result_is_the_kkt_projection_of_the_reduced_system(case, spva):
+    """With NNR (and SPVA) active, the result on the coefficients left free
+    is the Euclidean projection of the MCRT input onto the restrictions with
+    the removed columns deleted (App. A.1-A.2), computed here from the
+    optimality conditions rather than the null-space form of eq. 3.47-3.52;
+    the removed coefficients are exactly zero and none is negative."""
+    if case == "e1":
+        x, omega = E1["F1_mcrt"], E1["areas"]
+    else:
+        inst = W.small_box(3, 1, seed=11, rays=200)
+        x, omega = inst.f_noisy, inst.area
+    n = x.shape[0]
+    f, info = enforce_lsq(x, omega, nnr=True, spva=spva)
+    act = info["active"].reshape(-1)
+    if spva:
+        assert not act[x.reshape(-1) == 0.0].any()
+    a, b = restriction_matrix(n, omega)
+    y = _kkt_projection(a[:, act], b, x.reshape(-1)[act])
+    assert np.abs(f.reshape(-1)[act] - y).max() <= 1e-12
+    assert np.all(f.reshape(-1)[~act] == 0.0)
+    assert f.min() >= 0.0
+    if case == "e1" and not spva:
+        assert info["rounds"] > 1  # NNR removed coefficients that the plain projection made negative
