@@ -108,6 +108,27 @@ int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const double* area,
                        int32_t max_iter, void* work, size_t work_bytes,
                        rad_stats* stats, void* stream);
 
+/*
+ * Allocation-free variant of rad_enforce_vf, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same iteration, kernels and
+ * results as rad_enforce_vf, with the scratch taken from a fixed array of
+ * RAD_ENFORCE_NOALLOC_BYTES in device memory that the library reserves when
+ * it is loaded, one per GPU, held until the process ends.  n up to 16384
+ * fits (n for which rad_enforce_workspace_bytes(n) <= RAD_ENFORCE_NOALLOC_BYTES);
+ * a larger n returns RAD_EWORKSPACE with a message and enqueues nothing.
+ * The call allocates nothing; the caller passes F, area, n_rays as for
+ * rad_enforce_vf.  Every call on one GPU uses that GPU's single scratch
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads) race; serialise them.  The device of ``stream`` must
+ * be the current HIP device.
+ */
+#define RAD_ENFORCE_NOALLOC_BYTES ((size_t)36 << 20)
+int32_t rad_enforce_vf_noalloc(double* F, int64_t n, int64_t ldf,
+                               const double* area, const double* n_rays,
+                               int32_t kappa_mode, double tol, int32_t max_iter,
+                               rad_stats* stats, void* stream);
+
 /* ---- open-system Gebhart REF solve ------------------------------------- */
 /*
  * Gebhart's matrix method extended to open systems (Sec. 4.2.3, eq. 4.5;

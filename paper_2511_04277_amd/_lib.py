@@ -26,6 +26,7 @@ RAD_KAPPA_HALF = 1
 RAD_PREC_FP64 = 0
 RAD_PREC_FP32_IR = 1
 RAD_PREC_FP64_I8 = 2
+RAD_ENFORCE_NOALLOC_BYTES = 36 << 20
 RAD_LSQ_NNR = 1
 RAD_LSQ_SPVA = 2
 
@@ -105,6 +106,7 @@ SIGNATURES = {
     "rad_version": (_I32, []),
     "rad_enforce_workspace_bytes": (_SZ, [_I64]),
     "rad_enforce_vf": (_I32, [_P, _I64, _I64, _P, _P, _I32, _D, _I32, _P, _SZ, _STATS, _P]),
+    "rad_enforce_vf_noalloc": (_I32, [_P, _I64, _I64, _P, _P, _I32, _D, _I32, _STATS, _P]),
     "rad_gebhart_factor_bytes": (_SZ, [_I64, _I32]),
     "rad_gebhart_workspace_bytes": (_SZ, [_I64, _I32]),
     "rad_gebhart_ref": (_I32, [_P, _I64, _I64, _P, _P, _P, _I64, _I32, _D, _I32, _P, _SZ, _P, _SZ, _STATS, _P]),

@@ -19,6 +19,10 @@
 #include "enforce_kernels.h"
 
 #include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <mutex>
+#include <string>
 
 namespace rad {
 namespace {
@@ -59,27 +63,38 @@ extern "C" size_t rad_enforce_workspace_bytes(int64_t n) {
   return enf_layout(nullptr, 0, n).bytes;
 }
 
-extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const double* area,
-                                  const double* n_rays, int32_t kappa_mode, double tol,
-                                  int32_t max_iter, void* work, size_t work_bytes,
-                                  rad_stats* stats, void* stream) {
-  clear_error();
-  RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_enforce_vf: n out of range");
-  RAD_REQUIRE(ldf >= n + 1, RAD_EINVAL, "rad_enforce_vf: ldf < n+1");
-  RAD_REQUIRE(F && area, RAD_EINVAL, "rad_enforce_vf: NULL F or area");
-  RAD_REQUIRE(kappa_mode == RAD_KAPPA_FRACVAR || kappa_mode == RAD_KAPPA_HALF, RAD_EINVAL,
-              "rad_enforce_vf: unknown kappa_mode");
-  RAD_REQUIRE(kappa_mode == RAD_KAPPA_HALF || n_rays, RAD_EINVAL,
-              "rad_enforce_vf: n_rays required for RAD_KAPPA_FRACVAR");
-  RAD_REQUIRE(max_iter >= 1, RAD_EINVAL, "rad_enforce_vf: max_iter < 1");
-  RAD_REQUIRE(tol >= 0.0 && tol == tol, RAD_EINVAL, "rad_enforce_vf: tol < 0");
-  EnfLayout l = enf_layout(work, work_bytes, n);
-  RAD_REQUIRE(l.ok && (reinterpret_cast<uintptr_t>(work) % 256 == 0), RAD_EWORKSPACE,
-              "rad_enforce_vf: workspace too small or not 256-byte aligned");
+namespace rad {
+namespace {
+
+// Host-side argument checks shared by both entry points.
+int32_t enforce_check_args(const char* who, double* F, int64_t n, int64_t ldf, const double* area,
+                           const double* n_rays, int32_t kappa_mode, double tol, int32_t max_iter) {
+  static thread_local char msg[160];
+  auto fail = [&](int32_t code, const char* what) {
+    snprintf(msg, sizeof msg, "%s: %s", who, what);
+    set_error(msg);
+    return code;
+  };
+  if (!(n >= 1 && n <= (1 << 20))) return fail(RAD_EINVAL, "n out of range");
+  if (!(ldf >= n + 1)) return fail(RAD_EINVAL, "ldf < n+1");
+  if (!(F && area)) return fail(RAD_EINVAL, "NULL F or area");
+  if (!(kappa_mode == RAD_KAPPA_FRACVAR || kappa_mode == RAD_KAPPA_HALF))
+    return fail(RAD_EINVAL, "unknown kappa_mode");
+  if (!(kappa_mode == RAD_KAPPA_HALF || n_rays)) return fail(RAD_EINVAL, "n_rays required for RAD_KAPPA_FRACVAR");
+  if (!(max_iter >= 1)) return fail(RAD_EINVAL, "max_iter < 1");
+  if (!(tol >= 0.0 && tol == tol)) return fail(RAD_EINVAL, "tol < 0");
+  return RAD_OK;
+}
+
+// The iteration itself, on scratch laid out by enf_layout (either the
+// caller's workspace or the library's static scratch).
+int32_t enforce_run(const char* who, double* F, int64_t n, int64_t ldf, const double* area,
+                    const double* n_rays, int32_t kappa_mode, double tol, int32_t max_iter, const EnfLayout& l,
+                    rad_stats* stats, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int t = static_cast<int>(ceil_div(n, ET));
   const long pairs = static_cast<long>(t) * (t + 1) / 2;
-  RAD_REQUIRE(pairs < (1L << 31), RAD_EINVAL, "rad_enforce_vf: too many tiles");
+  RAD_REQUIRE(pairs < (1L << 31), RAD_EINVAL, std::string(who) + ": too many tiles");
   EnfInst in;
   in.F = F;
   in.ldf = static_cast<long>(ldf);
@@ -135,10 +150,88 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
   stats->closure_defect = h.last_defect;
   stats->recip_err = h.last_recip;
   if (h.status < 0) {
-    set_error(h.status == RAD_EZEROROW ? "rad_enforce_vf: a row of F sums to zero"
-                                       : "rad_enforce_vf: F has a negative or non-finite entry");
+    set_error(std::string(who) + (h.status == RAD_EZEROROW ? ": a row of F sums to zero"
+                                                           : ": F has a negative or non-finite entry"));
     return h.status;
   }
   if (tol > 0.0 && !h.converged) return RAD_WNOTCONVERGED;
   return RAD_OK;
+}
+
+// ---- the allocation-free variant ------------------------------------------
+// Its scratch is one array in device memory, reserved when the code object is
+// loaded and held by each GPU until the process ends; every call on a GPU
+// shares that GPU's copy.
+constexpr size_t ENF_NOALLOC_BYTES = RAD_ENFORCE_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[ENF_NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::atomic<void*> scratch_ptr[MAX_DEVICES];
+std::mutex scratch_mutex;
+
+// Device address of the current device's copy of ``scratch``, looked up once
+// per device (the array's host-side name is not a device address).
+int32_t scratch_for_current_device(void** out) {
+  int dev = -1;
+  RAD_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("rad_enforce_vf_noalloc: device ordinal beyond the supported range");
+    return RAD_EINVAL;
+  }
+  void* p = scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    p = scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      RAD_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p) {
+        set_error("rad_enforce_vf_noalloc: no device address for the static scratch");
+        return RAD_EHIP;
+      }
+      scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return RAD_OK;
+}
+
+}  // namespace
+}  // namespace rad
+
+extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const double* area,
+                                  const double* n_rays, int32_t kappa_mode, double tol,
+                                  int32_t max_iter, void* work, size_t work_bytes,
+                                  rad_stats* stats, void* stream) {
+  clear_error();
+  int32_t rc = enforce_check_args("rad_enforce_vf", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter);
+  if (rc != RAD_OK) return rc;
+  EnfLayout l = enf_layout(work, work_bytes, n);
+  RAD_REQUIRE(l.ok && (reinterpret_cast<uintptr_t>(work) % 256 == 0), RAD_EWORKSPACE,
+              "rad_enforce_vf: workspace too small or not 256-byte aligned");
+  return enforce_run("rad_enforce_vf", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter, l, stats, stream);
+}
+
+extern "C" int32_t rad_enforce_vf_noalloc(double* F, int64_t n, int64_t ldf, const double* area,
+                                          const double* n_rays, int32_t kappa_mode, double tol,
+                                          int32_t max_iter, rad_stats* stats, void* stream) {
+  clear_error();
+  int32_t rc = enforce_check_args("rad_enforce_vf_noalloc", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter);
+  if (rc != RAD_OK) return rc;
+  const size_t need = enf_layout(nullptr, 0, n).bytes;
+  if (need > ENF_NOALLOC_BYTES) {
+    static thread_local char msg[192];
+    snprintf(msg, sizeof msg,
+             "rad_enforce_vf_noalloc: n = %lld needs %zu bytes of scratch, more than the built-in %zu "
+             "(n <= 16384 fits); use rad_enforce_vf with a workspace",
+             static_cast<long long>(n), need, ENF_NOALLOC_BYTES);
+    set_error(msg);
+    return RAD_EWORKSPACE;
+  }
+  void* base = nullptr;
+  rc = scratch_for_current_device(&base);
+  if (rc != RAD_OK) return rc;
+  EnfLayout l = enf_layout(base, ENF_NOALLOC_BYTES, n);
+  RAD_REQUIRE(l.ok, RAD_EWORKSPACE, "rad_enforce_vf_noalloc: scratch layout failed");
+  return enforce_run("rad_enforce_vf_noalloc", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter, l, stats,
+                     stream);
 }
