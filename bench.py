@@ -50,6 +50,23 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+ROW_ALIGN = 16  # doubles: matrix rows start on 128-byte boundaries
+
+
+def padded_matrix(rows: int, cols: int, device, fill=None):
+    """An uninitialised (rows, cols) float64 view whose rows are ROW_ALIGN-double
+    aligned (leading dimension rounded up): the library takes any ld >= cols,
+    and 128-byte aligned rows keep each tile row of the enforcement sweep on
+    whole cache lines."""
+    import torch
+    ld = (cols + ROW_ALIGN - 1) // ROW_ALIGN * ROW_ALIGN
+    buf = torch.empty((rows, ld), dtype=torch.float64, device=device)
+    v = buf[:, :cols]
+    if fill is not None:
+        v.copy_(torch.as_tensor(fill, dtype=torch.float64).to(device))
+    return v
+
+
 def solve_flops(n: int) -> float:
     """Algorithmic flops of B = K^{-1} E: LU (2/3 n^3) + two triangular solves on n+1 columns."""
     return 2.0 / 3.0 * n ** 3 + 2.0 * n * n * (n + 1)
@@ -147,8 +164,8 @@ def main() -> int:
     def d(a, dt=torch.float64):
         return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
 
-    F0 = d(inst.f_noisy)
-    F = torch.empty_like(F0)
+    F0 = padded_matrix(n, n + 1, dev, inst.f_noisy)
+    F = padded_matrix(n, n + 1, dev)
     area, nrays, eps, rho = d(inst.area), d(inst.n_rays), d(inst.eps[0]), d(inst.rho[0])
     w_ref = eps * area
     grp1, grp2 = d(g1, torch.int32), d(g2, torch.int32)
@@ -160,9 +177,9 @@ def main() -> int:
     diff = np.empty((n, n + 1))
     diff[:, :n] = t4[:, None] - t4[None, :]
     diff[:, n] = t4 - T_SPACE ** 4
-    G = d(SIGMA * (inst.eps[0] * inst.area)[:, None] * diff)
+    G = padded_matrix(n, n + 1, dev, SIGMA * (inst.eps[0] * inst.area)[:, None] * diff)
     del diff
-    Bbuf = torch.empty((n, n + 1), dtype=torch.float64, device=dev)
+    Bbuf = padded_matrix(n, n + 1, dev)
     Y1 = torch.empty((n1, n1 + 1), dtype=torch.float64, device=dev)
     Y2 = torch.empty((n2, n2 + 1), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
@@ -241,7 +258,8 @@ def main() -> int:
         if k == 0:
             slots.append({"stream": main_stream, "F": F, "B": Bbuf, "fac": factors[prec], "Y1": Y1, "Y2": Y2})
         else:
-            slots.append({"stream": torch.cuda.Stream(), "F": torch.empty_like(F), "B": torch.empty_like(Bbuf),
+            slots.append({"stream": torch.cuda.Stream(), "F": padded_matrix(n, n + 1, dev),
+                          "B": padded_matrix(n, n + 1, dev),
                           "fac": rad.Factors(n, prec, dev), "Y1": torch.empty_like(Y1), "Y2": torch.empty_like(Y2)})
 
     def step(k=0):
@@ -507,8 +525,8 @@ def target_n16384(rad, oracle, W, d, reps: int = 3) -> dict:
     g1, g2 = inst.groups
     n1, n2 = int(g1.max()) + 1, int(g2.max()) + 1
     log(f"target n={n}: generated in {time.time() - t0:.1f}s")
-    F0 = d(inst.f_noisy)
-    F = torch.empty_like(F0)
+    F0 = padded_matrix(n, n + 1, "cuda", inst.f_noisy)
+    F = padded_matrix(n, n + 1, "cuda")
     area, nrays, eps, rho = d(inst.area), d(inst.n_rays), d(inst.eps[0]), d(inst.rho[0])
     F.copy_(F0)
     torch.cuda.synchronize()
@@ -523,7 +541,7 @@ def target_n16384(rad, oracle, W, d, reps: int = 3) -> dict:
     out = {"n": n, "workload": "open_box_n16384 (1x1x0.75 m, 1/64 m cells, 1e4 rays/face)",
            "enforce_iters": est["iters"], "enforce_ms": enf_ms, "enforce_closure_defect": est["closure_defect"],
            "enforce_recip_err": est["recip_err"], "solve": {}}
-    B = torch.empty((n, n + 1), dtype=torch.float64, device=F.device)
+    B = padded_matrix(n, n + 1, F.device)
     hosts = {}
     scale = None
     for name, (prec, ir_tol, ir_max) in (("fp64", ("fp64", 0.0, 0)), ("fp64_i8", ("fp64_i8", 0.0, 0)),
@@ -615,7 +633,7 @@ def two_sided_timing(rad, F, B, eps, area, d, reps: int = 5) -> dict:
     grp[perm[1::2]] = np.arange(n // 2)
     g = n // 2
     group = d(grp, torch.int32)
-    R = torch.empty_like(F)
+    R = padded_matrix(F.shape[0], F.shape[1], F.device)
     E = torch.empty((g, g + 1), dtype=torch.float64, device=F.device)
     rad.view_fractions(F, group, g, out=R)
     rad.node_emissivity(B, eps, area, group, g, out=E)
@@ -726,9 +744,9 @@ def run_batch64(args) -> int:
     def d(a):
         return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
 
-    f0 = [d(i.f_noisy) for i in insts]
-    models = [{"F": f.clone(), "area": d(i.area), "n_rays": d(i.n_rays), "eps": [d(e) for e in i.eps],
-               "rho": [d(r) for r in i.rho]} for f, i in zip(f0, insts)]
+    f0 = [padded_matrix(i.n, i.n + 1, dev, i.f_noisy) for i in insts]
+    models = [{"F": padded_matrix(i.n, i.n + 1, dev, f), "area": d(i.area), "n_rays": d(i.n_rays),
+               "eps": [d(e) for e in i.eps], "rho": [d(r) for r in i.rho]} for f, i in zip(f0, insts)]
     iters = 80
     variants = {"fp64": ("fp64", 0), "fp32_ir1": ("fp32_ir", 1)}
     if args.precision in ("fp32_ir", "fp32_ir1"):
@@ -742,8 +760,9 @@ def run_batch64(args) -> int:
     results = {}
     nslots = max(1, args.inflight)
     # one set of models (own F copies and outputs) per step in flight
-    slot_models = [models] + [[{"F": f.clone(), "area": m["area"], "n_rays": m["n_rays"], "eps": m["eps"],
-                                "rho": m["rho"]} for m, f in zip(models, f0)] for _ in range(nslots - 1)]
+    slot_models = [models] + [[{"F": padded_matrix(f.shape[0], f.shape[1], dev, f), "area": m["area"],
+                                "n_rays": m["n_rays"], "eps": m["eps"], "rho": m["rho"]} for m, f in zip(models, f0)]
+                              for _ in range(nslots - 1)]
     for name in wanted:
         prec, ir = variants[name]
         batches = [rad.Batch(ms_, precision=prec) for ms_ in slot_models]

@@ -103,6 +103,16 @@ inline hipError_t stream_wait(hipStream_t dst, hipStream_t src, hipEvent_t ev) {
 // smallest (most negative) code wins via atomicMin).
 __device__ inline void raise_status(int* flag, int code) { atomicMin(flag, code); }
 
+// The hardware hands workgroup k of a launch to XCD k % 8, and each XCD has
+// its own L2: this maps dispatch index pid to a logical index such that each
+// XCD owns a contiguous range of the total.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_contiguous(int pid, int total) {
+  const int q = total / NUM_XCD, rem = total % NUM_XCD;
+  const int x = pid % NUM_XCD, loc = pid / NUM_XCD;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + loc;
+}
+
 // tile pair (I, J), I <= J, of index p in the row-wise enumeration of the
 // upper triangle of a t x t tile grid
 __device__ inline void pair_from_index(long p, int t, int& I, int& J) {

@@ -47,32 +47,41 @@ constexpr int ERW = ET / ENW;  // tile rows per wave
 // one offset register serves every row.
 // (readfirstlane pins the row pointer to scalar registers, so the compiler
 // cannot fold the lane offset into a per-row vector address).
-__device__ __forceinline__ char* uniform_ptr(const double* p) {
+// The pointer is rebuilt in the global address space: a generic (flat)
+// pointer would make every access a flat instruction with a 64-bit address
+// per lane, which costs two registers per load in flight.
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gchar* uniform_ptr(const double* p) {
   const unsigned long long v = reinterpret_cast<unsigned long long>(p);
   const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
   const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
-  return reinterpret_cast<char*>((static_cast<unsigned long long>(hi) << 32) | lo);
+  return reinterpret_cast<gchar*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 // F streams through once per sweep (it is larger than the last-level cache
 // at the sizes that matter), so its loads and stores are nontemporal.
 __device__ __forceinline__ double row_ld(const double* row, unsigned col) {
-  return __builtin_nontemporal_load(reinterpret_cast<const double*>(uniform_ptr(row) + col * 8u));
+  return __builtin_nontemporal_load(reinterpret_cast<const gdouble*>(uniform_ptr(row) + col * 8u));
 }
 __device__ __forceinline__ void row_st(double* row, unsigned col, double v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<double*>(uniform_ptr(row) + col * 8u));
+  __builtin_nontemporal_store(v, reinterpret_cast<gdouble*>(uniform_ptr(row) + col * 8u));
 }
 
 // kappa of eq. 3.25 from the pair (f_ij, f_ji) and c = A^2 / N of both faces:
 // kappa = b / (a + b), a = c_i (1 - f_ij) f_ji, b = c_j (1 - f_ji) f_ij (the
 // variances of eq. 3.23 multiplied by F_ij F_ji); 1/2 when both vanish.
 // The quotient uses the hardware reciprocal refined by two Newton steps.
+// Every operation rounds as written (no contraction into fused multiply-adds
+// beyond the two explicit Newton steps), so the result does not depend on how
+// the compiler schedules the surrounding code.
 __device__ __forceinline__ double kappa_c(double fij, double fji, double ci, double cj) {
+#pragma clang fp contract(off)
   const double a = ci * (1.0 - fij) * fji;
   const double b = cj * (1.0 - fji) * fij;
   const double s = a + b;
   double r = __builtin_amdgcn_rcp(s);
-  r = r * (2.0 - s * r);
-  r = r * (2.0 - s * r);
+  r = r * __builtin_fma(-s, r, 2.0);
+  r = r * __builtin_fma(-s, r, 2.0);
   return s > 0.0 ? b * r : 0.5;
 }
 
@@ -88,61 +97,79 @@ __device__ __forceinline__ double kappa_c(double fij, double fji, double ci, dou
 // All sums run in a fixed order (bitwise reproducible).  DIAG: I == J (each
 // unordered pair once, the diagonal kept, the space column carried along);
 // EDGE: the tile pair crosses n (clamped loads, masked stores).
-template <bool DIAG, bool EDGE>
+template <bool DIAG, bool EDGE, bool HALF>
 __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int I, int J, int first,
                                                double (*sB)[ETP], double (*red)[ET], double (*rowc)[ET]) {
+#pragma clang fp contract(off)
   double* __restrict__ F = in.F;
   const long ldf = in.ldf;
   const int n = in.n;
   const double* __restrict__ area = in.area;
   const double* __restrict__ inv_area = in.inv_area;
   const double* __restrict__ nrays = in.nrays;
-  const bool half = in.mode == RAD_KAPPA_HALF;
+  const bool half = HALF;
   const double* __restrict__ inv_scale = in.scale;
   const int r0 = I * ET, c0 = J * ET;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   int bad = 0;
 
-  // per-row constants of tile row block I: area, 1 / area, A^2 / N, 1 / s
-  if (tid < ET) {
-    const int i = (EDGE && r0 + tid >= n) ? n - 1 : r0 + tid;
-    const double ai = area[i];
-    rowc[0][tid] = ai;
-    rowc[1][tid] = inv_area[i];
-    rowc[2][tid] = half ? 0.0 : ai * ai / nrays[i];
-    rowc[3][tid] = first ? 1.0 : inv_scale[i];
-  } else if (!DIAG && tid < 2 * ET) {  // 1 / s of the partner tile's rows
-    const int jr = (EDGE && c0 + tid - ET >= n) ? n - 1 : c0 + tid - ET;
-    rowc[4][tid - ET] = first ? 1.0 : inv_scale[jr];
-  }
-  __syncthreads();
-  // own tile (I, J): a[k] = F(r0 + w + ENW k, c0 + l).  Row pointers are
-  // wave-uniform and the lane adds its column, so loads use a scalar base.
+  // The tiles' loads go out first, so that their latency covers the loads
+  // of the per-row constants below.  Own tile (I, J): a[k] = F(r0 + w +
+  // ENW k, c0 + l); partner tile (J, I): b[k] = F(c0 + w + ENW k, r0 + l).
+  // Row pointers are wave-uniform and the lane adds its column, so loads
+  // use a scalar base.
   const int jg = c0 + l;
   const int jgc = (EDGE && jg >= n) ? n - 1 : jg;
-  double a[ERW];
+  const int ig = r0 + l;
+  const int igc = (EDGE && ig >= n) ? n - 1 : ig;
+  double a[ERW], b[ERW];
 #pragma unroll
   for (int k = 0; k < ERW; ++k) {
     const int i = r0 + w + ENW * k;
     const int ic = (EDGE && i >= n) ? n - 1 : i;
-    double v = row_ld(F + static_cast<long>(ic) * ldf, jgc);
-    if (EDGE && !(i < n && jg < n)) v = 0.0;
-    bad |= !(v >= 0.0) || !(v <= 1.0e300);
-    a[k] = v * rowc[3][w + ENW * k];
+    a[k] = row_ld(F + static_cast<long>(ic) * ldf, jgc);
   }
-  // partner tile (J, I) into LDS: sB[jl][il] = F(c0 + jl, r0 + il)
   if (!DIAG) {
-    const int ig = r0 + l;
-    const int igc = (EDGE && ig >= n) ? n - 1 : ig;
 #pragma unroll
     for (int k = 0; k < ERW; ++k) {
       const int jr = c0 + w + ENW * k;
       const int jrc = (EDGE && jr >= n) ? n - 1 : jr;
-      double v = row_ld(F + static_cast<long>(jrc) * ldf, igc);
+      b[k] = row_ld(F + static_cast<long>(jrc) * ldf, igc);
+    }
+  }
+  // per-row constants: area, 1 / area, A^2 / N and the previous closure
+  // scale 1 / s of the own tile's rows (rowc[0..3]) and of the partner
+  // tile's rows (rowc[4..7])
+  if (tid < (DIAG ? ET : 2 * ET)) {
+    const int q = tid < ET ? 0 : 4;
+    const int base = tid < ET ? r0 : c0;
+    const int rl = tid & (ET - 1);
+    const int i = (EDGE && base + rl >= n) ? n - 1 : base + rl;
+    const double ai = area[i];
+    rowc[q + 0][rl] = ai;
+    rowc[q + 1][rl] = inv_area[i];
+    rowc[q + 2][rl] = half ? 0.0 : ai * ai / nrays[i];
+    rowc[q + 3][rl] = first ? 1.0 : inv_scale[i];
+  }
+  __syncthreads();
+  // scaled by the positive finite 1 / s (1 on the first sweep); negative or
+  // non-finite inputs stay so and are caught where the pair is formed
+#pragma unroll
+  for (int k = 0; k < ERW; ++k) {
+    const int i = r0 + w + ENW * k;
+    double v = a[k];
+    if (EDGE && !(i < n && jg < n)) v = 0.0;
+    a[k] = v * rowc[3][w + ENW * k];
+  }
+  // partner tile into LDS: sB[jl][il] = F(c0 + jl, r0 + il)
+  if (!DIAG) {
+#pragma unroll
+    for (int k = 0; k < ERW; ++k) {
+      const int jr = c0 + w + ENW * k;
+      double v = b[k];
       if (EDGE && !(jr < n && ig < n)) v = 0.0;
-      bad |= !(v >= 0.0) || !(v <= 1.0e300);
-      sB[w + ENW * k][l] = v * rowc[4][w + ENW * k];
+      sB[w + ENW * k][l] = v * rowc[7][w + ENW * k];
     }
   } else {
 #pragma unroll
@@ -152,18 +179,23 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
 
   // reciprocity on each unordered pair {i, j}, i != j, exactly once
   double rmax = 0.0, emax = 0.0, sb = 0.0;
-  const double aj = area[jgc], iaj = inv_area[jgc];
-  const double cj = half ? 0.0 : aj * aj / nrays[jgc];
+  // constants of row c0 + l (the partner's row; on a diagonal tile the own rows)
+  const double aj = rowc[DIAG ? 0 : 4][l], iaj = rowc[DIAG ? 1 : 5][l];
+  const double cj = rowc[DIAG ? 2 : 6][l];
 #pragma unroll
   for (int k = 0; k < ERW; ++k) {
     const int il = w + ENW * k;
     const double ai = rowc[0][il];
     if (DIAG) {
-      if (l == il) emax = fmax(emax, ai * a[k]);  // the diagonal keeps its value
+      if (l == il) {                               // the diagonal keeps its value
+        emax = fmax(emax, ai * a[k]);
+        bad |= !(a[k] >= 0.0) || !(a[k] <= 1.0e300);
+      }
       if (l <= il) continue;                       // handled by the owner of (l, il)
     }
     const double iai = rowc[1][il];
     const double fij = a[k], fji = sB[l][il];
+    bad |= !(fij >= 0.0) || !(fij <= 1.0e300) || !(fji >= 0.0) || !(fji <= 1.0e300);
     const double eij = ai * fij, eji = aj * fji;
     rmax = fmax(rmax, fabs(eij - eji));
     emax = fmax(emax, fmax(eij, eji));
@@ -173,8 +205,10 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     a[k] = eh * iai;
     sB[l][il] = bji;
     sb += bji;
-    // keep the pair updates from being interleaved (register pressure)
-    __builtin_amdgcn_sched_barrier(0);
+    // fold this pair into the running maxima and the error flag now: left to
+    // itself the compiler keeps every pair's terms live and reduces them as a
+    // tree after the loop, which doubles the registers of the kernel
+    __asm__ volatile("" : "+v"(rmax), "+v"(emax), "+v"(bad), "+v"(sb));
   }
   __syncthreads();
   if (DIAG) {
@@ -253,23 +287,36 @@ __device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int
   if (in.ctrl->converged || in.ctrl->status < 0) return;
   __shared__ double sB[ET][ETP];
   __shared__ double red[2 * (ENW)][ET];  // per-wave row partials: partner, own
-  __shared__ double rowc[5][ET];                       // per-row constants
+  __shared__ double rowc[8][ET];  // per-row constants of the own and the partner tile
   int I, J;
   pair_from_index(pair, in.t, I, J);
   I = __builtin_amdgcn_readfirstlane(I);  // workgroup-uniform: keeps tile addressing scalar
   J = __builtin_amdgcn_readfirstlane(J);
   const bool edge = (I + 1) * ET > in.n || (J + 1) * ET > in.n;
-  if (I == J) {
-    if (edge) enf_sweep_tile<true, true>(in, pair, I, J, first, sB, red, rowc);
-    else enf_sweep_tile<true, false>(in, pair, I, J, first, sB, red, rowc);
+  if (in.mode == RAD_KAPPA_HALF) {
+    if (I == J) {
+      if (edge) enf_sweep_tile<true, true, true>(in, pair, I, J, first, sB, red, rowc);
+      else enf_sweep_tile<true, false, true>(in, pair, I, J, first, sB, red, rowc);
+    } else {
+      if (edge) enf_sweep_tile<false, true, true>(in, pair, I, J, first, sB, red, rowc);
+      else enf_sweep_tile<false, false, true>(in, pair, I, J, first, sB, red, rowc);
+    }
   } else {
-    if (edge) enf_sweep_tile<false, true>(in, pair, I, J, first, sB, red, rowc);
-    else enf_sweep_tile<false, false>(in, pair, I, J, first, sB, red, rowc);
+    if (I == J) {
+      if (edge) enf_sweep_tile<true, true, false>(in, pair, I, J, first, sB, red, rowc);
+      else enf_sweep_tile<true, false, false>(in, pair, I, J, first, sB, red, rowc);
+    } else {
+      if (edge) enf_sweep_tile<false, true, false>(in, pair, I, J, first, sB, red, rowc);
+      else enf_sweep_tile<false, false, false>(in, pair, I, J, first, sB, red, rowc);
+    }
   }
 }
 
-__global__ void __launch_bounds__(ENF_THREADS, 4) enf_sweep(EnfInst in, int first) {
-  enf_sweep_body(in, blockIdx.x, first);
+// Tile pairs in row order (I, I), (I, I + 1), ...: consecutive pairs share
+// the own tiles' rows, so each XCD takes a contiguous range of them and the
+// cache lines two neighbouring tiles share meet in one L2.
+__global__ void __launch_bounds__(ENF_THREADS, 6) enf_sweep(EnfInst in, int first) {
+  enf_sweep_body(in, xcd_contiguous(blockIdx.x, gridDim.x), first);
 }
 
 // index of the last entry of start[0..count) that is <= v
@@ -283,7 +330,7 @@ __device__ __forceinline__ int find_segment(const long* __restrict__ start, int 
 }
 
 // all instances of a batch in one grid: blocks [pair_start[k], pair_start[k+1]) are instance k
-__global__ void __launch_bounds__(ENF_THREADS, 4)
+__global__ void __launch_bounds__(ENF_THREADS, 6)
 enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair_start, int count, int first) {
   const int k = find_segment(pair_start, count, blockIdx.x);
   enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);

@@ -264,14 +264,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int bx, int by) 
 // makes the work per tile row differ (up to 8x), so those products walk whole
 // tile columns instead: each XCD then holds a range of columns with every
 // row, and all XCDs get the same work.
-constexpr int NUM_XCD = 8;
 constexpr int TILE_GROUP = 8;
-
-__device__ __forceinline__ int xcd_contiguous(int pid, int total) {
-  const int q = total / NUM_XCD, rem = total % NUM_XCD;
-  const int x = pid % NUM_XCD, loc = pid / NUM_XCD;
-  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + loc;
-}
 
 __device__ __forceinline__ void grouped_tile(int L, int ntx, int nty, int group, int& bx, int& by) {
   const int per = group * ntx;
