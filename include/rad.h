@@ -380,7 +380,9 @@ int32_t rad_absorbed_flux(const double* B, int64_t n, int64_t ldb,
  * defect max_i |s_i - 1| falls to enforce_tol > 0 stops early, decided on the
  * device; enforce_iters = 0 skips enforcement and solves F as given), then
  * the solves, with ir_steps FP64 refinement steps in RAD_PREC_FP32_IR mode
- * (ignored for RAD_PREC_FP64).  rad_batch_stats (host) waits for ``stream``
+ * (ignored for RAD_PREC_FP64 and RAD_PREC_FP64_I8; in RAD_PREC_FP64_I8 the
+ * K = 1024 products of problems larger than one 1024-wide panel run as int8
+ * digit products, as in rad_gebhart_ref, and give the same bits as it).  rad_batch_stats (host) waits for ``stream``
  * and fills out[0..count) per instance: iters, converged, closure_defect,
  * recip_err of the enforcement, the largest ir_residual / ir_correction over
  * the bands, device_status; it returns the most negative device status.

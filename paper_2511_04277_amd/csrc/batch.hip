@@ -19,6 +19,7 @@
 #include <cstring>
 #include <vector>
 
+#include "emu_kernels.h"
 #include "enforce_kernels.h"
 #include "gebhart_kernels.h"
 
@@ -32,7 +33,8 @@ struct rad_batch_plan {
   void* prepared_for = nullptr;
   // filled by layout()
   struct InstOff { size_t ctrl, scale, inv_area, blkmax, finred, partial; int t; long pairs; };
-  struct ProbOff { int inst, band, n, np, P2; long ldk, ldy, ldx, ldp, ldw, ldt; size_t kf, dinv, y, x, r, p, sc, w, v, scr; };
+  struct ProbOff { int inst, band, n, np, P2; long ldk, ldy, ldx, ldp, ldw, ldt; size_t kf, dinv, y, x, r, p, sc, w, v, scr;
+                   size_t da, db, xa, xb; };
   std::vector<InstOff> io;
   std::vector<ProbOff> po;
   size_t tables_off = 0;
@@ -47,7 +49,56 @@ struct rad_batch_plan {
 namespace rad {
 namespace {
 
-enum { L_GJ = 0, L_GEMM = 1, L_COPY = 2, L_TRI_INIT = 3 };
+enum { L_GJ = 0, L_GEMM = 1, L_COPY = 2, L_TRI_INIT = 3, L_EMU_EXP_KC = 4, L_EMU_FILL = 5, L_EMU_EXP_RC = 6,
+       L_EMU_SPLIT_KC = 7, L_EMU_SPLIT_RC = 8, L_EMU_GEMM = 9 };
+
+// One operand of the int8-emulated products of a batched launch (the digits
+// and exponents of each problem's operands have buffers of their own): the
+// operand's rows [0, 64 T), k blocks [0, nkb).
+struct EmuJob {
+  EmuOperand op;
+  int8_t* dig;
+  int* ex;
+  int T, nkb;
+};
+
+// scale exponents, k-contiguous rows: four rows per block
+__global__ void __launch_bounds__(256)
+b_emu_rowexp_kc(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const EmuJob& j = jobs[q];
+  emu_rowexp_kc_body(j.op, 0, j.T * EMU_TILE, j.ex, static_cast<int>(blockIdx.x - start[q]));
+}
+
+// exponents of rows-contiguous operands start at EMU_EXP_NONE (256 per block)
+__global__ void __launch_bounds__(256)
+b_emu_fill(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const EmuJob& j = jobs[q];
+  const int i = static_cast<int>(blockIdx.x - start[q]) * 256 + threadIdx.x;
+  if (i < j.T * EMU_TILE) j.ex[i] = EMU_EXP_NONE;
+}
+
+// scale exponents, rows contiguous: 256 rows x one k block per block
+__global__ void __launch_bounds__(256)
+b_emu_rowexp_rc(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
+  const int q = find_segment(start, count, blockIdx.x);
+  const EmuJob& j = jobs[q];
+  const int nbx = (j.T * EMU_TILE + 255) / 256;
+  const int b = static_cast<int>(blockIdx.x - start[q]);
+  emu_rowexp_rc_body(j.op, 0, j.T * EMU_TILE, j.ex, b % nbx, b / nbx);
+}
+
+// digits: one 64-row x 64-k block per block
+template <bool KC>
+__global__ void __launch_bounds__(256)
+b_emu_split(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
+  __shared__ double tile[EMU_TILE][EMU_KB + 1];
+  const int q = find_segment(start, count, blockIdx.x);
+  const EmuJob& j = jobs[q];
+  const int b = static_cast<int>(blockIdx.x - start[q]);
+  emu_split_body<EMU_S, KC>(j.op, j.T, b % j.T, b / j.T, j.ex, j.dig, tile);
+}
 
 // one row-block copy of a batched launch: rows [0, rows) of src -> dst, cols columns
 template <class T>
@@ -325,6 +376,83 @@ struct Sched {
     const auto& o = P->po[q];
     return TriJob<T>{kf(q), o.ldk, dinv(q), o.np, w(q), v(q), o.ldw, scr(q), o.ldt};
   }
+  // RAD_PREC_FP64_I8: the K = 1024 products of the outer updates and of the
+  // back substitution run as int8 digit products, as in the single solve
+  bool emu() const { return P->precision == RAD_PREC_FP64_I8; }
+  EmuJob emu_job(const EmuOperand& op, bool is_a, int q) {
+    const auto& o = P->po[q];
+    return EmuJob{op, reinterpret_cast<int8_t*>(base + (is_a ? o.da : o.db)),
+                  reinterpret_cast<int*>(base + (is_a ? o.xa : o.xb)), (op.R + EMU_TILE - 1) / EMU_TILE,
+                  (op.K + EMU_KB - 1) / EMU_KB};
+  }
+  // C(i, j) -= op(A) B over all tiles; column j < N0 of C0, then N1 of C1
+  static EmuGemmArgs emu_gemm_args(const EmuJob& a, const EmuJob& b, int M, int N0, double* C0, long ldc0, int N1,
+                                   double* C1, long ldc1) {
+    return EmuGemmArgs{a.dig, a.ex, b.dig, b.ex, a.T, b.T, a.nkb, 0, a.T, 0, b.T, M, -1.0, N1 > 0 ? 2 : 1,
+                       {N0, N1}, {C0, C1}, {ldc0, ldc1}};
+  }
+  void emit_jobs(std::vector<rad_batch_plan::Launch>& out, int kind, size_t off, const std::vector<long>& st,
+                 int count, double bytes) {
+    rad_batch_plan::Launch L{};
+    L.kind = kind;
+    L.count = count;
+    L.off = off;
+    L.off2 = tb->add(st.data(), st.size());
+    L.grid = static_cast<unsigned>(st.back());
+    L.bytes = bytes;
+    out.push_back(L);
+  }
+  // exponents and digits of every operand, then the products of every problem
+  void emit_emu(std::vector<rad_batch_plan::Launch>& out, std::vector<EmuJob>& kc, std::vector<EmuJob>& rc,
+                std::vector<EmuGemmArgs>& g, std::vector<double>& flops, std::vector<double>& bytes) {
+    for (int kind = 0; kind < 2; ++kind) {
+      std::vector<EmuJob>& jobs = kind == 0 ? kc : rc;
+      if (jobs.empty()) continue;
+      const size_t off = tb->add(jobs.data(), jobs.size());
+      const int cnt = static_cast<int>(jobs.size());
+      std::vector<long> s_exp(1, 0), s_fill(1, 0), s_split(1, 0);
+      double elems = 0.0;
+      for (const EmuJob& j : jobs) {
+        const long rows = static_cast<long>(j.T) * EMU_TILE;
+        s_exp.push_back(s_exp.back() + (kind == 0 ? (rows + 3) / 4 : (rows + 255) / 256 * j.nkb));
+        s_fill.push_back(s_fill.back() + (rows + 255) / 256);
+        s_split.push_back(s_split.back() + static_cast<long>(j.T) * j.nkb);
+        elems += static_cast<double>(j.op.R) * j.op.K;
+      }
+      // algorithmic bytes of the split as in the single solve: read 8, write 7 per element
+      if (kind == 0) {
+        emit_jobs(out, L_EMU_EXP_KC, off, s_exp, cnt, 0.0);
+        emit_jobs(out, L_EMU_SPLIT_KC, off, s_split, cnt, (8.0 + EMU_S) * elems);
+      } else {
+        emit_jobs(out, L_EMU_FILL, off, s_fill, cnt, 0.0);
+        emit_jobs(out, L_EMU_EXP_RC, off, s_exp, cnt, 0.0);
+        emit_jobs(out, L_EMU_SPLIT_RC, off, s_split, cnt, (8.0 + EMU_S) * elems);
+      }
+      jobs.clear();
+    }
+    if (g.empty()) return;
+    std::vector<int> st(g.size() + 1, 0);
+    double f = 0.0, b = 0.0;
+    for (size_t k = 0; k < g.size(); ++k) {
+      st[k + 1] = st[k] + g[k].ntx * g[k].nty;
+      f += flops[k];
+      b += bytes[k];
+    }
+    rad_batch_plan::Launch L{};
+    L.kind = L_EMU_GEMM;
+    L.count = static_cast<int>(g.size());
+    L.off = tb->add(g.data(), g.size());
+    L.off2 = tb->add(st.data(), st.size());
+    L.grid = std::min<unsigned>(static_cast<unsigned>(st.back()), 2 * 256);
+    L.flops = f;
+    L.bytes = b;
+    if (st.back() > 0) out.push_back(L);
+    g.clear();
+    flops.clear();
+    bytes.clear();
+  }
+  static double emu_flops(int M, int N, int K) { return 2.0 * M * N * K; }
+  static double emu_bytes(int M, int N, int K) { return 16.0 * M * N + EMU_S * (static_cast<double>(M) + N) * K; }
   void emit_rows(std::vector<rad_batch_plan::Launch>& out, int kind, size_t off, std::vector<long>& rs, int count) {
     rad_batch_plan::Launch L{};
     L.kind = kind;
@@ -426,6 +554,33 @@ struct Sched {
       }
       emit_gemm(out, g, false);
     }
+    if constexpr (std::is_same<T, double>::value) {
+      if (emu() && with_k) {  // L block (k contiguous), then U block and right-hand sides (rows contiguous)
+        std::vector<EmuJob> kc, rc;
+        std::vector<EmuGemmArgs> eg;
+        std::vector<double> ef, eb;
+        for (int q = 0; q < P->nprob; ++q) {
+          const auto& o = P->po[q];
+          const int c0 = pan * NB2;
+          if (c0 >= o.np) continue;
+          const int c1 = std::min(c0 + NB2, o.np);
+          if (c1 >= o.np) continue;
+          const int M = o.np - c1, K = c1 - c0;
+          const EmuOperand oa{{kf(q) + static_cast<long>(c1) * o.ldk + c0, nullptr}, {o.ldk, 0}, {1, 0}, M, M, K};
+          const EmuOperand ob{{kf(q) + static_cast<long>(c0) * o.ldk + c1, y(q) + static_cast<long>(c0) * o.ldy},
+                              {1, 1}, {o.ldk, o.ldy}, M, M + o.n + 1, K};
+          const EmuJob ja = emu_job(oa, true, q), jb = emu_job(ob, false, q);
+          kc.push_back(ja);
+          rc.push_back(jb);
+          eg.push_back(emu_gemm_args(ja, jb, M, M, kf(q) + static_cast<long>(c1) * o.ldk + c1, o.ldk, o.n + 1,
+                                     y(q) + static_cast<long>(c1) * o.ldy, o.ldy));
+          ef.push_back(emu_flops(M, M + o.n + 1, K));
+          eb.push_back(emu_bytes(M, M + o.n + 1, K));
+        }
+        emit_emu(out, kc, rc, eg, ef, eb);
+        return;
+      }
+    }
     for (int q = 0; q < P->nprob; ++q) {
       const auto& o = P->po[q];
       const int c0 = pan * NB2;
@@ -497,6 +652,30 @@ struct Sched {
       }
       emit_gemm(P->back, g, false);
       if (!cj.empty()) emit_rows(P->back, L_COPY, tb->add(cj.data(), cj.size()), rs, static_cast<int>(cj.size()));
+      if constexpr (std::is_same<T, double>::value) {
+        if (emu()) {  // rows above the panel: U's column block (k contiguous) times the panel's rows of Y
+          std::vector<EmuJob> kc, rc;
+          std::vector<EmuGemmArgs> eg;
+          std::vector<double> ef, eb;
+          for (int q = 0; q < P->nprob; ++q) {
+            const auto& o = P->po[q];
+            const int pan = o.P2 - 1 - rp;
+            if (pan <= 0) continue;
+            const int c0 = pan * NB2, c1 = std::min(c0 + NB2, o.np), K = c1 - c0;
+            const EmuOperand oa{{kf(q) + c0, nullptr}, {o.ldk, 0}, {1, 0}, c0, c0, K};
+            const EmuOperand ob{{y(q) + static_cast<long>(c0) * o.ldy, nullptr}, {1, 0}, {o.ldy, 0}, o.n + 1,
+                                o.n + 1, K};
+            const EmuJob ja = emu_job(oa, true, q), jb = emu_job(ob, false, q);
+            kc.push_back(ja);
+            rc.push_back(jb);
+            eg.push_back(emu_gemm_args(ja, jb, c0, o.n + 1, y(q), o.ldy, 0, nullptr, 0));
+            ef.push_back(emu_flops(c0, o.n + 1, K));
+            eb.push_back(emu_bytes(c0, o.n + 1, K));
+          }
+          emit_emu(P->back, kc, rc, eg, ef, eb);
+          continue;
+        }
+      }
       for (int q = 0; q < P->nprob; ++q) {  // rows above the panel
         const auto& o = P->po[q];
         const int pan = o.P2 - 1 - rp;
@@ -527,7 +706,7 @@ struct Sched {
   }
 };
 
-size_t elem(int prec) { return prec == RAD_PREC_FP64 ? 8 : 4; }
+size_t elem(int prec) { return prec == RAD_PREC_FP32_IR ? 4 : 8; }
 
 // buffer layout of the workspace (tables come last, see build_tables)
 void layout(rad_batch_plan* P) {
@@ -574,6 +753,13 @@ void layout(rad_batch_plan* P) {
       o.w = take(static_cast<size_t>(o.P2) * NB2 * o.ldw * es);
       o.v = take(static_cast<size_t>(o.P2) * NB2 * o.ldw * es);
       o.scr = take(std::max(static_cast<size_t>(NB2) * o.ldy, tri_tmp_elems(o.P2, static_cast<long>(128 / es))) * es);
+      if (P->precision == RAD_PREC_FP64_I8 && o.np > NB2) {  // operands of the emulated K = 1024 products
+        const long rb = static_cast<long>(o.np) + o.n + 1;
+        o.da = take(emu_digit_bytes(o.np, NB2));
+        o.db = take(emu_digit_bytes(rb, NB2));
+        o.xa = take(emu_scale_count(o.np) * sizeof(int));
+        o.xb = take(emu_scale_count(rb) * sizeof(int));
+      }
       if (P->precision == RAD_PREC_FP32_IR) {
         o.x = take(static_cast<size_t>(o.np) * o.ldx * 8);
         o.r = take(static_cast<size_t>(o.np) * o.ldx * 8);
@@ -665,7 +851,7 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
   P->off_pd = tb.add(pd.data(), pd.size());
   P->off_nprow = tb.add(nprow.data(), nprow.size());
   P->off_nrow = tb.add(nrow.data(), nrow.size());
-  if (P->precision == RAD_PREC_FP64) {
+  if (P->precision != RAD_PREC_FP32_IR) {
     Sched<double> sch{P, base, &tb};
     sch.factor();
     sch.panel_inverses();
@@ -683,7 +869,26 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
 template <class T>
 hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const char* tables, hipStream_t s) {
   for (const auto& L : ls) {
-    if (L.kind == L_COPY) {
+    if (L.kind >= L_EMU_EXP_KC && L.kind <= L_EMU_SPLIT_RC) {
+      const EmuJob* jobs = reinterpret_cast<const EmuJob*>(tables + L.off);
+      const long* st = reinterpret_cast<const long*>(tables + L.off2);
+      ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0, L.bytes);
+      if (L.kind == L_EMU_EXP_KC)
+        hipLaunchKernelGGL(b_emu_rowexp_kc, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
+      else if (L.kind == L_EMU_FILL)
+        hipLaunchKernelGGL(b_emu_fill, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
+      else if (L.kind == L_EMU_EXP_RC)
+        hipLaunchKernelGGL(b_emu_rowexp_rc, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
+      else if (L.kind == L_EMU_SPLIT_KC)
+        hipLaunchKernelGGL(b_emu_split<true>, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
+      else
+        hipLaunchKernelGGL(b_emu_split<false>, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
+    } else if (L.kind == L_EMU_GEMM) {
+      ProfScope prof(s, RAD_PROF_GEMM_I8X, L.flops, L.bytes);
+      hipLaunchKernelGGL(emu_gemm_grouped<EMU_S>, dim3(L.grid), dim3(EMU_THREADS), 0, s,
+                         reinterpret_cast<const EmuGemmArgs*>(tables + L.off),
+                         reinterpret_cast<const int*>(tables + L.off2), L.count);
+    } else if (L.kind == L_COPY) {
       hipLaunchKernelGGL(b_copy_jobs<T>, dim3(L.grid), dim3(256), 0, s,
                          reinterpret_cast<const CopyJob<T>*>(tables + L.off),
                          reinterpret_cast<const long*>(tables + L.off2), L.count);
@@ -729,8 +934,8 @@ extern "C" int32_t rad_batch_plan_create(const rad_instance* inst, int32_t count
   RAD_REQUIRE(plan && work_bytes, RAD_EINVAL, "rad_batch_plan_create: NULL output");
   *plan = nullptr;
   RAD_REQUIRE(inst && count >= 1 && count <= (1 << 16), RAD_EINVAL, "rad_batch_plan_create: bad instance list");
-  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP32_IR, RAD_EINVAL,
-              "rad_batch_plan_create: unknown precision");
+  RAD_REQUIRE(precision == RAD_PREC_FP64 || precision == RAD_PREC_FP32_IR || precision == RAD_PREC_FP64_I8,
+              RAD_EINVAL, "rad_batch_plan_create: unknown precision");
   RAD_REQUIRE(kappa_mode == RAD_KAPPA_FRACVAR || kappa_mode == RAD_KAPPA_HALF, RAD_EINVAL,
               "rad_batch_plan_create: unknown kappa_mode");
   for (int i = 0; i < count; ++i) {
@@ -815,7 +1020,7 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
   // ---- Gebhart solves of every (instance, band)
   hipLaunchKernelGGL(b_scalars_init, dim3(qb), dim3(64), 0, s, pd, Q, 1);
   const unsigned npr = static_cast<unsigned>(P->total_nprow), nr = static_cast<unsigned>(P->total_nrow);
-  if (P->precision == RAD_PREC_FP64) {
+  if (P->precision != RAD_PREC_FP32_IR) {
     hipLaunchKernelGGL(b_form<double>, dim3(npr), dim3(256), 0, s, pd, nprow, Q);
     RAD_HIP_CHECK(run_launches<double>(P->factor, tables, s));
     RAD_HIP_CHECK(run_launches<double>(P->back, tables, s));

@@ -77,8 +77,9 @@ __device__ __forceinline__ double emu_load(const EmuOperand& op, int r, int k) {
 
 // Scale exponents e_r (max_k |X_rk| < 2^e_r; EMU_EXP_NONE for a zero row) of
 // rows [r0, r1).  k-contiguous rows: one wave per row.
-static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
-  const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void emu_rowexp_kc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ ex,
+                                                   int blk) {
+  const int r = r0 + blk * 4 + (threadIdx.x >> 6);
   const int l = threadIdx.x & 63;
   if (r >= r1) return;
   double m = 0.0;
@@ -90,12 +91,17 @@ static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r
   if (l == 0) ex[r] = m > 0.0 ? e : EMU_EXP_NONE;
 }
 
+static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
+  emu_rowexp_kc_body(op, r0, r1, ex, blockIdx.x);
+}
+
 // Rows contiguous in memory: a workgroup takes 256 rows x 64 k (each thread
 // one row, every load instruction 512 contiguous bytes) and merges its
 // exponents by atomic maxima; ex must hold EMU_EXP_NONE beforehand.
-static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
-  const int r = r0 + blockIdx.x * 256 + threadIdx.x;
-  const int k0 = blockIdx.y * EMU_KB;
+__device__ __forceinline__ void emu_rowexp_rc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ ex,
+                                                   int bx, int by) {
+  const int r = r0 + bx * 256 + threadIdx.x;
+  const int k0 = by * EMU_KB;
   if (r >= r1) return;
   double m = 0.0;
 #pragma unroll 8
@@ -105,6 +111,10 @@ static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r
     frexp(m, &e);
     atomicMax(&ex[r], e);
   }
+}
+
+static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
+  emu_rowexp_rc_body(op, r0, r1, ex, blockIdx.x, blockIdx.y);
 }
 
 static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, int n, int v) {
@@ -118,10 +128,9 @@ static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, 
 // forms the S digits of 16 consecutive k of row t / 4 (chunk c = t % 4), and a
 // wave's stores of one slice are one contiguous 1 KB piece of the block.
 template <int S, bool KC>
-__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, const int* __restrict__ ex,
-                                                 int8_t* __restrict__ out) {
-  __shared__ double tile[EMU_TILE][EMU_KB + 1];
-  const int rt = rt0 + blockIdx.x, kb = blockIdx.y;
+__device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int rt, int kb,
+                                               const int* __restrict__ ex, int8_t* __restrict__ out,
+                                               double (*tile)[EMU_KB + 1]) {
   const int t = threadIdx.x;
   const int r0 = rt * EMU_TILE, k0 = kb * EMU_KB;
 #pragma unroll
@@ -155,6 +164,13 @@ __global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, 
   for (int s = 0; s < S; ++s) blk[emu_lds_idx(s, row, c)] = dg[s].v;
 }
 
+template <int S, bool KC>
+__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, const int* __restrict__ ex,
+                                                 int8_t* __restrict__ out) {
+  __shared__ double tile[EMU_TILE][EMU_KB + 1];
+  emu_split_body<S, KC>(op, T, rt0 + blockIdx.x, blockIdx.y, ex, out, tile);
+}
+
 // ---- the product --------------------------------------------------------
 
 struct EmuGemmArgs {
@@ -181,13 +197,9 @@ struct EmuGemmArgs {
 // MFMAs run from registers meanwhile into S int32 class accumulators that
 // persist over the whole K.
 template <int S>
-__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
+__device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int by,
+                                              emu_v4i (*lds)[S * EMU_TILE * 4]) {
   constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
-  __shared__ emu_v4i lds[2][CH];        // [A, B][chunk]
-  int bx, by;
-  grouped_tile(xcd_contiguous(blockIdx.x, g.ntx * g.nty), g.ntx, g.nty, TILE_GROUP, bx, by);
-  bx += g.tx0;
-  by += g.ty0;
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const emu_v4i* ga = reinterpret_cast<const emu_v4i*>(g.A) + static_cast<long>(by) * CH;
@@ -270,6 +282,36 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
         double* p = Cc + static_cast<long>(row) * ldc;
         *p = fma(g.alpha, ldexp(x, ea + eb), *p);
       }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
+  __shared__ emu_v4i lds[2][S * EMU_TILE * 4];  // [A, B][chunk]
+  int bx, by;
+  grouped_tile(xcd_contiguous(blockIdx.x, g.ntx * g.nty), g.ntx, g.nty, TILE_GROUP, bx, by);
+  emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
+}
+
+// Many products in one persistent launch (the batched solves): workgroups
+// walk the concatenated tile list (prefix sums in tile_start) in list order.
+// A workgroup starts its next tile's copies only after every wave has read
+// the last k block of the previous tile (the barrier after the fragment reads).
+template <int S>
+__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm_grouped(const EmuGemmArgs* __restrict__ probs,
+                                                                   const int* __restrict__ tile_start, int nprob) {
+  __shared__ emu_v4i lds[2][S * EMU_TILE * 4];
+  const int total = tile_start[nprob];
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const EmuGemmArgs& g = probs[lo];
+    int bx, by;
+    grouped_tile(b - tile_start[lo], g.ntx, g.nty, TILE_GROUP, bx, by);
+    emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
   }
 }
 

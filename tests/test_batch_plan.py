@@ -31,13 +31,20 @@ def _create(insts, precision=_lib.RAD_PREC_FP32_IR, kappa=_lib.RAD_KAPPA_FRACVAR
 def test_plan_sizes_cover_every_problem():
     lib = _lib.lib()
     ns = [300, 129, 1000, 64, 2100]
-    for prec in (_lib.RAD_PREC_FP64, _lib.RAD_PREC_FP32_IR):
+    sizes = {}
+    for prec in (_lib.RAD_PREC_FP64, _lib.RAD_PREC_FP32_IR, _lib.RAD_PREC_FP64_I8):
         code, plan, wb = _create([_inst(n, bands=1 + (k % 2)) for k, n in enumerate(ns)], prec)
         assert code == _lib.RAD_OK
         # at least the factor buffers of every (instance, band) problem
         need = sum((1 + (k % 2)) * lib.rad_gebhart_factor_bytes(n, prec) for k, n in enumerate(ns))
         assert wb > need
+        sizes[prec] = wb
         lib.rad_batch_plan_destroy(plan)
+    # the int8-emulated mode adds digit buffers for the problems past one
+    # 1024-wide panel (n = 2100 here: 7 digits of a 2176 x 1024 and a
+    # (2176 + 2101) x 1024 operand), nothing else
+    digits = 7 * 1024 * (2176 + (2176 + 2101 + 63) // 64 * 64)
+    assert sizes[_lib.RAD_PREC_FP64_I8] >= sizes[_lib.RAD_PREC_FP64] + digits
 
 
 def test_plan_rejects_bad_instances():

@@ -36,7 +36,7 @@ def _models(insts):
     return models, f0
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "fp64_i8"])
 def test_batch_matches_oracle(precision):
     need_gpu()
     import paper_2511_04277_amd as rad
@@ -46,7 +46,7 @@ def test_batch_matches_oracle(precision):
     batch = rad.Batch(models, precision=precision)
     batch.run(enforce_iters=ITERS, ir_steps=2)
     stats = batch.stats()
-    tol = TOL64 if precision == "fp64" else TOL_IR
+    tol = TOL64 if precision == "fp64" else TOL_IR  # fp32_ir: two refinement steps; fp64_i8: digit products
     for k, inst in enumerate(insts):
         f_ref, info = oracle.enforce_vf(inst.f_noisy, inst.area, inst.n_rays, "fracvar", tol=0.0, max_iter=ITERS)
         f_gpu = host(models[k]["F"])
@@ -59,7 +59,7 @@ def test_batch_matches_oracle(precision):
             assert err <= tol, (inst.name, b, err)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "fp64_i8"])
 def test_batch_equals_single_model_path(precision):
     need_gpu()
     import paper_2511_04277_amd as rad
@@ -94,12 +94,13 @@ def test_batch_tolerance_stops_each_instance():
         assert torch.equal(F, m["F"])
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("precision", ["fp32_ir", "fp64_i8"])
+def test_batch_graph_replays_match_eager(precision):
     need_gpu()
     import paper_2511_04277_amd as rad
     insts = _instances()
     models, f0 = _models(insts)
-    batch = rad.Batch(models, precision="fp32_ir")
+    batch = rad.Batch(models, precision=precision)
 
     def step():
         for k, m in enumerate(models):
