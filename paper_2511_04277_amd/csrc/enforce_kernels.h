@@ -381,10 +381,13 @@ __device__ __forceinline__ void enf_decide_body(const EnfInst& in, double tol) {
   }
 }
 
-// Row sums s_i of the (t + 1) partials of each row: 8 lanes per row take
-// every 8th partial, then combine over the lane masks 1, 2, 4 (fixed order).
-// Each block's maxima go to finred; the block that finishes last (a counter
-// in the control block, one atomic per block) reduces them and decides.
+// Row sums s_i of the (t + 1) partials of each row: part p = 0..7 of a row
+// sums every 8th partial (q = p, p + 8, ...) in order, then the eight parts
+// combine as ((0 + 1) + (2 + 3)) + ((4 + 5) + (6 + 7)) (fixed order).  Thread
+// t takes part t / 32 of row t % 32, so each load instruction of a wave reads
+// two 256-byte runs of consecutive rows of one partial.  Each block's maxima
+// go to finred; the block that finishes last (a counter in the control
+// block, one atomic per block) reduces them and decides.
 
 __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, int nblocks, double tol) {
   const int n = in.n, t = in.t;
@@ -394,20 +397,31 @@ __device__ __forceinline__ void enf_finalize_body(const EnfInst& in, int blk, in
   const long nblk = in.pairs;
   EnfCtrl* ctrl = in.ctrl;
   if (ctrl->converged || ctrl->status < 0) return;
-  const int part = threadIdx.x % FIN_LANES;
-  const int i = blk * FIN_ROWS + threadIdx.x / FIN_LANES;
+  __shared__ double ps[FIN_LANES][FIN_ROWS];
+  const int part = threadIdx.x / FIN_ROWS;
+  const int r = threadIdx.x % FIN_ROWS;
+  const int i = blk * FIN_ROWS + r;
   double s = 0.0;
-  if (i < n)
-    for (int q = part; q <= t; q += FIN_LANES) s += partial[static_cast<long>(q) * n + i];
-  s += __shfl_xor(s, 1);
-  s += __shfl_xor(s, 2);
-  s += __shfl_xor(s, 4);
-  double d = 0.0;
   if (i < n) {
-    if (part == 0) {
-      if (!(s > 0.0)) raise_status(&ctrl->status, RAD_EZEROROW);
-      scale[i] = 1.0 / s;
+    const double* __restrict__ col = partial + i;
+    int q = part;
+    // eight loads in flight; the sum still runs over q in increasing order
+    for (; q + 7 * FIN_LANES <= t; q += 8 * FIN_LANES) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[static_cast<long>(q + u * FIN_LANES) * n];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
     }
+    for (; q <= t; q += FIN_LANES) s += col[static_cast<long>(q) * n];
+  }
+  ps[part][r] = s;
+  __syncthreads();
+  double d = 0.0;
+  if (part == 0 && i < n) {
+    s = ((ps[0][r] + ps[1][r]) + (ps[2][r] + ps[3][r])) + ((ps[4][r] + ps[5][r]) + (ps[6][r] + ps[7][r]));
+    if (!(s > 0.0)) raise_status(&ctrl->status, RAD_EZEROROW);
+    scale[i] = 1.0 / s;
     d = fabs(s - 1.0);
   }
   double rm = 0.0, em = 0.0;
