@@ -132,6 +132,88 @@ agg_reduce(const double* __restrict__ X, long ldx, int n, const double* __restri
   if (gw && H == 0) gw[G] = wsum;
 }
 
+// The same sums with one workgroup per row group G and each member row of G
+// staged whole in LDS: the row is read once with coalesced loads, and the
+// column groups' gathers hit LDS instead of scattered HBM lines.  Thread t
+// owns the outputs H = t, t + AGGL_THREADS, ... (at most HPT of them) in
+// registers; every sum runs in the same member order as agg_reduce, so both
+// give the same bits.  Used when a row of X fits in AGGL_MAX_LDS.
+constexpr int AGGL_THREADS = 512;
+constexpr size_t AGGL_MAX_LDS = 150 * 1024;
+
+template <int HPT>
+__global__ void __launch_bounds__(AGGL_THREADS)
+agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const double* __restrict__ w,
+               const int* __restrict__ offs, const int* __restrict__ members, int g,
+               double* __restrict__ Y, long ldy, double* __restrict__ gw, int divide) {
+  extern __shared__ double xrow[];  // n + 1
+  const int G = blockIdx.x;
+  const int rb = offs[G], re = offs[G + 1];
+  double acc[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
+  double wsum = 0.0;
+  for (int a = rb; a < re; ++a) {
+    const int i = members[a];
+    const double wi = w[i];
+    wsum += wi;
+    const double* row = X + static_cast<long>(i) * ldx;
+    __syncthreads();  // the previous row's gathers are done
+    for (int j = threadIdx.x; j <= n; j += AGGL_THREADS) xrow[j] = __builtin_nontemporal_load(row + j);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int H = threadIdx.x + k * AGGL_THREADS;
+      if (H < g) {
+        const int cb = offs[H], ce = offs[H + 1];
+        double sv = 0.0;
+        for (int b = cb; b < ce; ++b) sv += xrow[members[b]];
+        acc[k] += wi * sv;
+      } else if (H == g) {
+        acc[k] += wi * xrow[n];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int H = threadIdx.x + k * AGGL_THREADS;
+    if (H <= g) Y[static_cast<long>(G) * ldy + H] = divide ? acc[k] / wsum : acc[k];
+  }
+  if (gw && threadIdx.x == 0) gw[G] = wsum;
+}
+
+// agg_reduce_lds when the row fits in LDS and the outputs in registers, else agg_reduce
+void launch_agg(const double* X, long ldx, int n, const double* w, const int* offs, const int* members, int g,
+                double* Y, long ldy, double* gw, int divide, hipStream_t s) {
+  const size_t lds = static_cast<size_t>(n + 1) * sizeof(double);
+  const int hpt = (g + AGGL_THREADS) / AGGL_THREADS;  // ceil((g + 1) / AGGL_THREADS)
+  if (lds <= AGGL_MAX_LDS && hpt <= 32) {
+    // dynamic LDS beyond the default 64 KB has to be allowed per kernel
+    auto allow = [](const void* fn) {
+      return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(AGGL_MAX_LDS)) ==
+             hipSuccess;
+    };
+    const void* fn = hpt <= 4    ? reinterpret_cast<const void*>(&agg_reduce_lds<4>)
+                     : hpt <= 16 ? reinterpret_cast<const void*>(&agg_reduce_lds<16>)
+                                 : reinterpret_cast<const void*>(&agg_reduce_lds<32>);
+    if (lds <= 64 * 1024 || allow(fn)) {
+      if (hpt <= 4)
+        hipLaunchKernelGGL(agg_reduce_lds<4>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx, n,
+                           w, offs, members, g, Y, ldy, gw, divide);
+      else if (hpt <= 16)
+        hipLaunchKernelGGL(agg_reduce_lds<16>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx,
+                           n, w, offs, members, g, Y, ldy, gw, divide);
+      else
+        hipLaunchKernelGGL(agg_reduce_lds<32>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx,
+                           n, w, offs, members, g, Y, ldy, gw, divide);
+      return;
+    }
+    (void)hipGetLastError();  // the attribute was refused: the gather form below
+  }
+  dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
+  hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, ldx, n, w, offs, members, g, Y, ldy, gw, divide);
+}
+
 __global__ void __launch_bounds__(256) zero_ints(int* __restrict__ p, long count) {
   for (long q = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; q < count;
        q += static_cast<long>(gridDim.x) * blockDim.x)
@@ -253,9 +335,8 @@ void agg_build(const int32_t* group, int n, int g, const AggLayout& l, hipStream
 
 void agg_sums(const double* X, long ldx, int n, const double* w, const AggLayout& l, int g, double* Y, long ldy,
               double* gw, hipStream_t s) {
-  dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
   ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
-  hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, ldx, n, w, l.offs, l.members, g, Y, ldy, gw, 0);
+  launch_agg(X, ldx, n, w, l.offs, l.members, g, Y, ldy, gw, 0, s);
 }
 
 int read_status(const int* dev, hipStream_t s, int* out) {
@@ -329,12 +410,10 @@ extern "C" int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
   hipLaunchKernelGGL(csr_offsets, dim3(1), dim3(1024), 0, s, l.cnt, l.nch, gi, l.offs, l.status);
   hipLaunchKernelGGL(csr_scatter, dim3(static_cast<unsigned>(ceil_div(n, 256))), dim3(256), 0, s, group, ni, gi,
                      l.rank, l.cnt, l.offs, l.members);
-  dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
   {
     ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
-    hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, static_cast<long>(ldx),
-                       static_cast<int>(n), weight, l.offs, l.members, static_cast<int>(g), Y,
-                       static_cast<long>(ldy), group_weight, 1);
+    launch_agg(X, static_cast<long>(ldx), ni, weight, l.offs, l.members, gi, Y, static_cast<long>(ldy),
+               group_weight, 1, s);
   }
   RAD_HIP_CHECK(hipGetLastError());
   if (!stats) return RAD_OK;
