@@ -81,6 +81,8 @@ TRAFFIC = {
                     [os.path.join(_CSRC, "emu_kernels.h")]),
     "ahf_partial<16, 2, 4, true>": (os.path.join(ROOT, "profiles", "ahf_partial_open_box_n8192_traffic.txt"),
                                     [os.path.join(_CSRC, "ahf.hip")]),
+    "enf_sweep": (os.path.join(ROOT, "profiles", "enf_sweep_open_box_n8192_traffic.txt"),
+                  [os.path.join(_CSRC, "enforce_kernels.h")]),
 }
 
 
@@ -194,12 +196,14 @@ def main() -> int:
     F_enf_host = F.cpu().numpy()
 
     # ---- plain copy of known size: scale for the HBM traffic counters -----
-    # (reads and writes n (n+1) doubles; a counter run divides the copy's
-    # FETCH_SIZE / WRITE_SIZE by these bytes to calibrate the GEMM's)
-    Fcal = torch.empty_like(F0)
-    torch.mul(F0, 1.0, out=Fcal)
+    # (the multiply reads and writes n (n+1) contiguous doubles; a counter
+    # run divides its FETCH_SIZE / WRITE_SIZE by these bytes to calibrate the
+    # other kernels')
+    Fsrc = F0.contiguous()
+    Fcal = torch.empty_like(Fsrc)
+    torch.mul(Fsrc, 1.0, out=Fcal)
     torch.cuda.synchronize()
-    del Fcal
+    del Fcal, Fsrc
 
     # ---- Gebhart alone: FP64, FP64 with int8 digit products, FP32 + FP64
     # refinement (one step, whose error is measured against the oracle
@@ -370,6 +374,8 @@ def main() -> int:
     sw = profs_all[L.PROFILE_KINDS.index("enforce_sweep")]
     if sw.launches:
         kern["enforce_sweep"]["hbm_frac"] = (sw.bytes / (sw.total_ms * 1e-3) / 1e9) / PEAK_HBM_GBS
+        kern["enforce_sweep"]["traffic"] = measured_traffic("enf_sweep", prec)
+        kern["enforce_sweep"]["algorithmic_bytes_per_launch"] = sw.bytes / sw.launches
     ahf = absorbed_flux_timing(rad, L, lib, slots[0]["B"], eps, rho, area, d(W.rng_for(8192, 2).uniform(
         0.0, 1400.0, (n, AHF_CASES))))
     log(f"absorbed flux ({AHF_CASES} cases): {ahf['ms']:.3f} ms per call, kernel {ahf['kernel_us']:.1f} us "
