@@ -389,6 +389,7 @@ extern "C" int32_t rad_aggregate_nodes(const double* X, int64_t n, int64_t ldx,
                                        const double* weight, const int32_t* group, int64_t g,
                                        double* Y, int64_t ldy, double* group_weight, void* work,
                                        size_t work_bytes, rad_stats* stats, void* stream) {
+  ApiRange range("rad_aggregate_nodes");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= (1 << 24), RAD_EINVAL, "rad_aggregate_nodes: n out of range");
   RAD_REQUIRE(g >= 1 && g <= n, RAD_EINVAL, "rad_aggregate_nodes: g must be in [1, n]");
@@ -437,6 +438,7 @@ extern "C" size_t rad_view_fractions_workspace_bytes(int64_t nf, int64_t g) {
 extern "C" int32_t rad_view_fractions(const double* F, int64_t nf, int64_t ldf, const int32_t* group, int64_t g,
                                       double* R, int64_t ldr, void* work, size_t work_bytes, rad_stats* stats,
                                       void* stream) {
+  ApiRange range("rad_view_fractions");
   clear_error();
   RAD_REQUIRE(nf >= 1 && nf <= (1 << 24), RAD_EINVAL, "rad_view_fractions: nf out of range");
   RAD_REQUIRE(g >= 1 && g <= nf, RAD_EINVAL, "rad_view_fractions: g must be in [1, nf]");
@@ -487,6 +489,7 @@ extern "C" int32_t rad_node_emissivity(const double* B, int64_t nf, int64_t ldb,
                                        const double* area, const int32_t* group, int64_t g, double* E,
                                        int64_t lde, void* work, size_t work_bytes, rad_stats* stats,
                                        void* stream) {
+  ApiRange range("rad_node_emissivity");
   clear_error();
   RAD_REQUIRE(nf >= 1 && nf <= (1 << 24), RAD_EINVAL, "rad_node_emissivity: nf out of range");
   RAD_REQUIRE(g >= 1 && g <= nf, RAD_EINVAL, "rad_node_emissivity: g must be in [1, nf]");

@@ -173,6 +173,7 @@ extern "C" int32_t rad_absorbed_flux(const double* B, int64_t n, int64_t ldb, co
                                      const double* rho, const double* area, const double* Qd, int64_t m,
                                      int64_t ldq, double* Qa, int64_t lda, void* work, size_t work_bytes,
                                      void* stream) {
+  ApiRange range("rad_absorbed_flux");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_absorbed_flux: n out of range");
   RAD_REQUIRE(m >= 1 && m <= RAD_AHF_MAX_CASES, RAD_EINVAL, "rad_absorbed_flux: m outside [1, RAD_AHF_MAX_CASES]");

@@ -930,6 +930,7 @@ using namespace rad;
 
 extern "C" int32_t rad_batch_plan_create(const rad_instance* inst, int32_t count, int32_t precision,
                                          int32_t kappa_mode, rad_batch_plan** plan, size_t* work_bytes) {
+  ApiRange range("rad_batch_plan_create");
   clear_error();
   RAD_REQUIRE(plan && work_bytes, RAD_EINVAL, "rad_batch_plan_create: NULL output");
   *plan = nullptr;
@@ -967,6 +968,7 @@ extern "C" int32_t rad_batch_plan_create(const rad_instance* inst, int32_t count
 extern "C" void rad_batch_plan_destroy(rad_batch_plan* plan) { delete plan; }
 
 extern "C" int32_t rad_batch_prepare(rad_batch_plan* P, void* work, size_t work_bytes, void* stream) {
+  ApiRange range("rad_batch_prepare");
   clear_error();
   RAD_REQUIRE(P, RAD_EINVAL, "rad_batch_prepare: NULL plan");
   RAD_REQUIRE(work && work_bytes >= P->work_bytes && reinterpret_cast<uintptr_t>(work) % 256 == 0,
@@ -983,6 +985,7 @@ extern "C" int32_t rad_batch_prepare(rad_batch_plan* P, void* work, size_t work_
 
 extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enforce_tol, int32_t enforce_iters,
                                  int32_t ir_steps, void* stream) {
+  ApiRange range("rad_batch_run");
   clear_error();
   RAD_REQUIRE(P && work, RAD_EINVAL, "rad_batch_run: NULL plan or workspace");
   RAD_REQUIRE(P->prepared_for == work, RAD_EINVAL, "rad_batch_run: workspace was not prepared with this plan");
@@ -1052,6 +1055,7 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
 }
 
 extern "C" int32_t rad_batch_stats(const rad_batch_plan* P, const void* work, rad_stats* out, void* stream) {
+  ApiRange range("rad_batch_stats");
   clear_error();
   RAD_REQUIRE(P && work && out, RAD_EINVAL, "rad_batch_stats: NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);

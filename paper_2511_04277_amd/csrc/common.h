@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -55,6 +56,16 @@ struct Carve {
     used = off + bytes;
     return reinterpret_cast<T*>(base + off);
   }
+};
+
+// One C-ABI call as a named roctx range, so that a marker trace
+// (rocprofv3 --marker-trace) shows each call around the kernels it enqueued.
+// Without an attached tool the push and pop return at once.
+struct ApiRange {
+  explicit ApiRange(const char* name) { roctxRangePushA(name); }
+  ~ApiRange() { roctxRangePop(); }
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
 };
 
 // Per-launch kernel timing (see profile.hip).

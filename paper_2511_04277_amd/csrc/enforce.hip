@@ -202,6 +202,7 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
                                   const double* n_rays, int32_t kappa_mode, double tol,
                                   int32_t max_iter, void* work, size_t work_bytes,
                                   rad_stats* stats, void* stream) {
+  ApiRange range("rad_enforce_vf");
   clear_error();
   int32_t rc = enforce_check_args("rad_enforce_vf", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter);
   if (rc != RAD_OK) return rc;
@@ -214,6 +215,7 @@ extern "C" int32_t rad_enforce_vf(double* F, int64_t n, int64_t ldf, const doubl
 extern "C" int32_t rad_enforce_vf_noalloc(double* F, int64_t n, int64_t ldf, const double* area,
                                           const double* n_rays, int32_t kappa_mode, double tol,
                                           int32_t max_iter, rad_stats* stats, void* stream) {
+  ApiRange range("rad_enforce_vf_noalloc");
   clear_error();
   int32_t rc = enforce_check_args("rad_enforce_vf_noalloc", F, n, ldf, area, n_rays, kappa_mode, tol, max_iter);
   if (rc != RAD_OK) return rc;

@@ -631,6 +631,7 @@ extern "C" int32_t rad_gebhart_ref(const double* F, int64_t n, int64_t ldf, cons
                                    const double* rho, double* B, int64_t ldb, int32_t precision,
                                    double ir_tol, int32_t ir_max, void* factors, size_t fbytes,
                                    void* work, size_t wbytes, rad_stats* stats, void* stream) {
+  ApiRange range("rad_gebhart_ref");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_gebhart_ref: n out of range");
   RAD_REQUIRE(ldf >= n + 1 && ldb >= n + 1, RAD_EINVAL, "rad_gebhart_ref: ldf or ldb < n+1");
@@ -727,6 +728,7 @@ extern "C" int32_t rad_steady_temperature(const double* Y, int64_t n, int64_t ld
                                           double t_space, double sigma, double* T, int64_t ldt,
                                           int32_t precision, void* factors, size_t fbytes, void* work,
                                           size_t wbytes, rad_stats* stats, void* stream) {
+  ApiRange range("rad_steady_temperature");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_steady_temperature: n out of range");
   RAD_REQUIRE(m >= 1 && m <= RAD_STEADY_MAX_CASES, RAD_EINVAL,
@@ -810,6 +812,7 @@ extern "C" int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf, cons
                                    int64_t ldo, int32_t flags, int32_t max_rounds, int32_t precision,
                                    void* factors, size_t fbytes, void* work, size_t wbytes, rad_stats* stats,
                                    void* stream) {
+  ApiRange range("rad_enforce_lsq");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= 65535, RAD_EINVAL, "rad_enforce_lsq: n out of range (1..65535)");
   RAD_REQUIRE(ldf >= n + 1 && ldo >= n + 1, RAD_EINVAL, "rad_enforce_lsq: ldf or ldo < n+1");
@@ -886,6 +889,7 @@ extern "C" size_t rad_ref_check_workspace_bytes(int64_t n) {
 extern "C" int32_t rad_ref_check(const double* B, int64_t n, int64_t ldb, const double* eps,
                                  const double* area, double* out, void* work, size_t wbytes,
                                  void* stream) {
+  ApiRange range("rad_ref_check");
   clear_error();
   RAD_REQUIRE(n >= 1 && ldb >= n + 1, RAD_EINVAL, "rad_ref_check: bad n or ldb");
   RAD_REQUIRE(B && eps && area && out, RAD_EINVAL, "rad_ref_check: NULL pointer");
@@ -918,6 +922,7 @@ extern "C" int32_t rad_gebhart_ref_adjoint(const void* factors, size_t fbytes, i
                                            double* grad_eps, double* grad_rho, double* Lambda,
                                            int64_t ldl, double ir_tol, int32_t ir_max, void* work,
                                            size_t wbytes, rad_stats* stats, void* stream) {
+  ApiRange range("rad_gebhart_ref_adjoint");
   clear_error();
   RAD_REQUIRE(n >= 1 && n <= (1 << 20), RAD_EINVAL, "rad_gebhart_ref_adjoint: n out of range");
   RAD_REQUIRE(ldf >= n + 1 && ldb >= n + 1 && ldg >= n + 1 && (!Lambda || ldl >= n + 1), RAD_EINVAL,

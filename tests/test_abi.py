@@ -75,3 +75,16 @@ def test_precision_size_queries():
         n, _lib.RAD_PREC_FP64)
     for q in (lib.rad_gebhart_factor_bytes, lib.rad_gebhart_workspace_bytes, lib.rad_adjoint_workspace_bytes):
         assert q(n, 3) == 0 and q(0, _lib.RAD_PREC_FP64_I8) == 0
+
+
+def test_calls_are_marked_as_roctx_ranges():
+    # every compute entry point opens a named roctx range (marker traces)
+    import subprocess
+    syms = subprocess.run(["nm", "-D", "--undefined-only", str(_lib.LIB_PATH)], capture_output=True, text=True,
+                          check=True).stdout
+    assert "roctxRangePushA" in syms and "roctxRangePop" in syms
+    src = "\n".join(p.read_text() for p in sorted((ROOT / "paper_2511_04277_amd" / "csrc").glob("*.hip")))
+    for name in ("rad_enforce_vf", "rad_enforce_vf_noalloc", "rad_gebhart_ref", "rad_gebhart_ref_adjoint",
+                 "rad_ref_check", "rad_aggregate_nodes", "rad_absorbed_flux", "rad_enforce_lsq", "rad_view_fractions",
+                 "rad_node_emissivity", "rad_steady_temperature", "rad_batch_prepare", "rad_batch_run"):
+        assert f'ApiRange range("{name}")' in src, name
