@@ -96,6 +96,10 @@ int32_t rad_version(void);
  * max_iter is reached first); tol == 0 runs exactly max_iter iterations and
  * needs no host synchronisation (graph-capturable when stats == NULL).
  *
+ * F:      any ldf >= n+1 works; rows that start on 128-byte boundaries
+ *         (F 128-byte aligned, ldf a multiple of 16) let every tile row
+ *         load touch only its own cache lines, which makes a sweep about
+ *         25 % faster at n = 8192 than ldf = n+1.
  * area:   n face areas A_i > 0.
  * n_rays: n rays emitted per face (> 0); may be NULL for RAD_KAPPA_HALF.
  * work:   >= rad_enforce_workspace_bytes(n).
