@@ -34,7 +34,7 @@ struct rad_batch_plan {
   // filled by layout()
   struct InstOff { size_t ctrl, scale, inv_area, blkmax, finred, partial; int t; long pairs; };
   struct ProbOff { int inst, band, n, np, P2; long ldk, ldy, ldx, ldp, ldw, ldt; size_t kf, dinv, y, x, r, p, sc, w, v, scr;
-                   size_t da, db, xa, xb; };
+                   size_t da, db, xa, xb, pa, pb; };
   std::vector<InstOff> io;
   std::vector<ProbOff> po;
   size_t tables_off = 0;
@@ -49,16 +49,18 @@ struct rad_batch_plan {
 namespace rad {
 namespace {
 
-enum { L_GJ = 0, L_GEMM = 1, L_COPY = 2, L_TRI_INIT = 3, L_EMU_EXP_KC = 4, L_EMU_FILL = 5, L_EMU_EXP_RC = 6,
-       L_EMU_SPLIT_KC = 7, L_EMU_SPLIT_RC = 8, L_EMU_GEMM = 9 };
+enum { L_GJ = 0, L_GEMM = 1, L_COPY = 2, L_TRI_INIT = 3, L_EMU_EXP_KC = 4, L_EMU_EXP_RC = 5, L_EMU_SPLIT_KC = 6,
+       L_EMU_SPLIT_RC = 7, L_EMU_GEMM = 8 };
 
 // One operand of the int8-emulated products of a batched launch (the digits
 // and exponents of each problem's operands have buffers of their own): the
-// operand's rows [0, 64 T), k blocks [0, nkb).
+// operand's rows [0, 64 T), k blocks [0, nkb); part: per-k-block exponents
+// of a rows-contiguous operand.
 struct EmuJob {
   EmuOperand op;
   int8_t* dig;
   int* ex;
+  int* part;
   int T, nkb;
 };
 
@@ -70,15 +72,6 @@ b_emu_rowexp_kc(const EmuJob* __restrict__ jobs, const long* __restrict__ start,
   emu_rowexp_kc_body(j.op, 0, j.T * EMU_TILE, j.ex, static_cast<int>(blockIdx.x - start[q]));
 }
 
-// exponents of rows-contiguous operands start at EMU_EXP_NONE (256 per block)
-__global__ void __launch_bounds__(256)
-b_emu_fill(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
-  const int q = find_segment(start, count, blockIdx.x);
-  const EmuJob& j = jobs[q];
-  const int i = static_cast<int>(blockIdx.x - start[q]) * 256 + threadIdx.x;
-  if (i < j.T * EMU_TILE) j.ex[i] = EMU_EXP_NONE;
-}
-
 // scale exponents, rows contiguous: 256 rows x one k block per block
 __global__ void __launch_bounds__(256)
 b_emu_rowexp_rc(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
@@ -86,7 +79,7 @@ b_emu_rowexp_rc(const EmuJob* __restrict__ jobs, const long* __restrict__ start,
   const EmuJob& j = jobs[q];
   const int nbx = (j.T * EMU_TILE + 255) / 256;
   const int b = static_cast<int>(blockIdx.x - start[q]);
-  emu_rowexp_rc_body(j.op, 0, j.T * EMU_TILE, j.ex, b % nbx, b / nbx);
+  emu_rowexp_rc_body(j.op, 0, j.T * EMU_TILE, j.part, static_cast<long>(j.T) * EMU_TILE, b % nbx, b / nbx);
 }
 
 // digits: one 64-row x 64-k block per block
@@ -97,7 +90,7 @@ b_emu_split(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int
   const int q = find_segment(start, count, blockIdx.x);
   const EmuJob& j = jobs[q];
   const int b = static_cast<int>(blockIdx.x - start[q]);
-  emu_split_body<EMU_S, KC>(j.op, j.T, b % j.T, b / j.T, j.ex, j.dig, tile);
+  emu_split_body<EMU_S, KC>(j.op, j.T, b % j.T, b / j.T, j.ex, j.part, j.nkb, j.dig, tile);
 }
 
 // one row-block copy of a batched launch: rows [0, rows) of src -> dst, cols columns
@@ -382,7 +375,8 @@ struct Sched {
   EmuJob emu_job(const EmuOperand& op, bool is_a, int q) {
     const auto& o = P->po[q];
     return EmuJob{op, reinterpret_cast<int8_t*>(base + (is_a ? o.da : o.db)),
-                  reinterpret_cast<int*>(base + (is_a ? o.xa : o.xb)), (op.R + EMU_TILE - 1) / EMU_TILE,
+                  reinterpret_cast<int*>(base + (is_a ? o.xa : o.xb)),
+                  reinterpret_cast<int*>(base + (is_a ? o.pa : o.pb)), (op.R + EMU_TILE - 1) / EMU_TILE,
                   (op.K + EMU_KB - 1) / EMU_KB};
   }
   // C(i, j) -= op(A) B over all tiles; column j < N0 of C0, then N1 of C1
@@ -410,12 +404,11 @@ struct Sched {
       if (jobs.empty()) continue;
       const size_t off = tb->add(jobs.data(), jobs.size());
       const int cnt = static_cast<int>(jobs.size());
-      std::vector<long> s_exp(1, 0), s_fill(1, 0), s_split(1, 0);
+      std::vector<long> s_exp(1, 0), s_split(1, 0);
       double elems = 0.0;
       for (const EmuJob& j : jobs) {
         const long rows = static_cast<long>(j.T) * EMU_TILE;
         s_exp.push_back(s_exp.back() + (kind == 0 ? (rows + 3) / 4 : (rows + 255) / 256 * j.nkb));
-        s_fill.push_back(s_fill.back() + (rows + 255) / 256);
         s_split.push_back(s_split.back() + static_cast<long>(j.T) * j.nkb);
         elems += static_cast<double>(j.op.R) * j.op.K;
       }
@@ -424,7 +417,6 @@ struct Sched {
         emit_jobs(out, L_EMU_EXP_KC, off, s_exp, cnt, 0.0);
         emit_jobs(out, L_EMU_SPLIT_KC, off, s_split, cnt, (8.0 + EMU_S) * elems);
       } else {
-        emit_jobs(out, L_EMU_FILL, off, s_fill, cnt, 0.0);
         emit_jobs(out, L_EMU_EXP_RC, off, s_exp, cnt, 0.0);
         emit_jobs(out, L_EMU_SPLIT_RC, off, s_split, cnt, (8.0 + EMU_S) * elems);
       }
@@ -759,6 +751,8 @@ void layout(rad_batch_plan* P) {
         o.db = take(emu_digit_bytes(rb, NB2));
         o.xa = take(emu_scale_count(o.np) * sizeof(int));
         o.xb = take(emu_scale_count(rb) * sizeof(int));
+        o.pa = take(emu_part_count(o.np, NB2) * sizeof(int));
+        o.pb = take(emu_part_count(rb, NB2) * sizeof(int));
       }
       if (P->precision == RAD_PREC_FP32_IR) {
         o.x = take(static_cast<size_t>(o.np) * o.ldx * 8);
@@ -875,8 +869,6 @@ hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const cha
       ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0, L.bytes);
       if (L.kind == L_EMU_EXP_KC)
         hipLaunchKernelGGL(b_emu_rowexp_kc, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
-      else if (L.kind == L_EMU_FILL)
-        hipLaunchKernelGGL(b_emu_fill, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
       else if (L.kind == L_EMU_EXP_RC)
         hipLaunchKernelGGL(b_emu_rowexp_rc, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
       else if (L.kind == L_EMU_SPLIT_KC)

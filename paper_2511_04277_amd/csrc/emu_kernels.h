@@ -96,30 +96,26 @@ static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r
 }
 
 // Rows contiguous in memory: a workgroup takes 256 rows x 64 k (each thread
-// one row, every load instruction 512 contiguous bytes) and merges its
-// exponents by atomic maxima; ex must hold EMU_EXP_NONE beforehand.
-__device__ __forceinline__ void emu_rowexp_rc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ ex,
-                                                   int bx, int by) {
+// one row, every load instruction 512 contiguous bytes) and stores the
+// exponent of each row's k block kb = by in part[kb Rp + r] (Rp: the
+// operand's padded row count); the digit pass takes the maximum over the
+// k blocks, so no atomics and no initial fill are needed.
+__device__ __forceinline__ void emu_rowexp_rc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ part,
+                                                   long Rp, int bx, int by) {
   const int r = r0 + bx * 256 + threadIdx.x;
   const int k0 = by * EMU_KB;
   if (r >= r1) return;
   double m = 0.0;
 #pragma unroll 8
   for (int k = k0; k < k0 + EMU_KB; ++k) m = fmax(m, fabs(emu_load(op, r, k)));
-  if (m > 0.0) {
-    int e = 0;
-    frexp(m, &e);
-    atomicMax(&ex[r], e);
-  }
+  int e = EMU_EXP_NONE;
+  if (m > 0.0) frexp(m, &e);
+  part[by * Rp + r] = e;
 }
 
-static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
-  emu_rowexp_rc_body(op, r0, r1, ex, blockIdx.x, blockIdx.y);
-}
-
-static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, int n, int v) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = v;
+static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ part,
+                                                            long Rp) {
+  emu_rowexp_rc_body(op, r0, r1, part, Rp, blockIdx.x, blockIdx.y);
 }
 
 // Digits of one 64-row x 64-k block per workgroup (row tile rt0 + blockIdx.x
@@ -127,9 +123,13 @@ static __global__ __launch_bounds__(256) void emu_fill_i32(int* __restrict__ p, 
 // whichever orientation the operand has and transposed through LDS; thread t
 // forms the S digits of 16 consecutive k of row t / 4 (chunk c = t % 4), and a
 // wave's stores of one slice are one contiguous 1 KB piece of the block.
+// k-contiguous operands read their exponents from ex; rows-contiguous ones
+// take the maximum of the nkb per-k-block exponents in part (layout of
+// emu_rowexp_rc, Rp = 64 T), and the workgroups of k block 0 store it in ex
+// for the product.
 template <int S, bool KC>
-__device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int rt, int kb,
-                                               const int* __restrict__ ex, int8_t* __restrict__ out,
+__device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int rt, int kb, int* __restrict__ ex,
+                                               const int* __restrict__ part, int nkb, int8_t* __restrict__ out,
                                                double (*tile)[EMU_KB + 1]) {
   const int t = threadIdx.x;
   const int r0 = rt * EMU_TILE, k0 = kb * EMU_KB;
@@ -140,9 +140,17 @@ __device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int 
     const int k = KC ? e % EMU_KB : e / EMU_TILE;
     tile[row][k] = emu_load(op, r0 + row, k0 + k);
   }
-  __syncthreads();
   const int row = t >> 2, c = t & 3;
-  const int e = ex[r0 + row];
+  int e;
+  if (KC) {
+    e = ex[r0 + row];
+  } else {
+    const long Rp = static_cast<long>(T) * EMU_TILE;
+    e = EMU_EXP_NONE;
+    for (int q = 0; q < nkb; ++q) e = max(e, part[q * Rp + r0 + row]);
+    if (kb == 0 && c == 0) ex[r0 + row] = e;
+  }
+  __syncthreads();
   const int es = e == EMU_EXP_NONE ? 0 : e;
   union {
     emu_v4i v;
@@ -165,10 +173,10 @@ __device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int 
 }
 
 template <int S, bool KC>
-__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, const int* __restrict__ ex,
-                                                 int8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, int* __restrict__ ex,
+                                                 const int* __restrict__ part, int8_t* __restrict__ out) {
   __shared__ double tile[EMU_TILE][EMU_KB + 1];
-  emu_split_body<S, KC>(op, T, rt0 + blockIdx.x, blockIdx.y, ex, out, tile);
+  emu_split_body<S, KC>(op, T, rt0 + blockIdx.x, blockIdx.y, ex, part, gridDim.y, out, tile);
 }
 
 // ---- the product --------------------------------------------------------
@@ -326,8 +334,10 @@ inline size_t emu_digit_bytes(long R, long K) {
 // contiguous in memory, else rows; t1 < 0: up to the last tile).  ex receives
 // one exponent per padded row; the digits land where the whole operand's
 // layout puts them, so disjoint tile ranges may be prepared by separate calls.
-inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, hipStream_t s, int t0 = 0,
-                              int t1 = -1) {
+// A rows-contiguous operand needs part, emu_part_count(R, K) ints of scratch
+// (per-k-block exponents).
+inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, int* part, hipStream_t s,
+                              int t0 = 0, int t1 = -1) {
   const int T = (op.R + EMU_TILE - 1) / EMU_TILE;
   const int nkb = (op.K + EMU_KB - 1) / EMU_KB;
   if (t1 < 0 || t1 > T) t1 = T;
@@ -335,17 +345,25 @@ inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* e
   const int r0 = t0 * EMU_TILE, r1 = t1 * EMU_TILE, nr = r1 - r0;
   if (kc) {
     hipLaunchKernelGGL(emu_rowexp_kc, dim3((nr + 3) / 4), dim3(256), 0, s, op, r0, r1, ex);
-    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex, dig);
+    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex,
+                       static_cast<const int*>(nullptr), dig);
   } else {
-    hipLaunchKernelGGL(emu_fill_i32, dim3((nr + 255) / 256), dim3(256), 0, s, ex + r0, nr, EMU_EXP_NONE);
-    hipLaunchKernelGGL(emu_rowexp_rc, dim3((nr + 255) / 256, nkb), dim3(256), 0, s, op, r0, r1, ex);
-    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex, dig);
+    if (!part) return hipErrorInvalidValue;
+    const long Rp = static_cast<long>(T) * EMU_TILE;
+    hipLaunchKernelGGL(emu_rowexp_rc, dim3((nr + 255) / 256, nkb), dim3(256), 0, s, op, r0, r1, part, Rp);
+    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex,
+                       static_cast<const int*>(part), dig);
   }
   return hipGetLastError();
 }
 
 // Entries of the exponent array of an operand with R rows.
 inline size_t emu_scale_count(long R) { return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE; }
+
+// Entries of the per-k-block exponent scratch of a rows-contiguous operand.
+inline size_t emu_part_count(long R, long K) {
+  return emu_scale_count(R) * static_cast<size_t>((K + EMU_KB - 1) / EMU_KB);
+}
 
 inline hipError_t emu_launch(const EmuGemmArgs& g, hipStream_t s) {
   if (g.ntx <= 0 || g.nty <= 0 || g.nkb <= 0) return hipSuccess;

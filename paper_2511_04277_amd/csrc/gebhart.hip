@@ -71,6 +71,8 @@ struct EmuWork {
   int8_t* db;  // digits of B^T
   int* xa;     // scale exponents of the rows of op(A)
   int* xb;     // scale exponents of the columns of B
+  int* pa;     // per-k-block exponents of op(A) when its rows are not k-contiguous
+  int* pb;     // per-k-block exponents of B's columns
 };
 
 // Scale exponents and digits of op(A) (if oa) and of B's row tiles
@@ -85,14 +87,15 @@ inline hipError_t emu_split_ops(const EmuWork& e, const EmuOperand* oa, bool akc
                                bt0 * static_cast<double>(EMU_TILE)) * ob->K;
   }
   ProfScope prof(s, RAD_PROF_I8X_SPLIT, 0.0, (8.0 + EMU_S) * elems);
+  // the buffers hold operands of K <= NB2 (one panel)
   if (oa) {
-    if (oa->K > EMU_MAX_K) return hipErrorInvalidValue;
-    hipError_t err = emu_prepare(*oa, akc, e.da, e.xa, s);
+    if (oa->K > NB2) return hipErrorInvalidValue;
+    hipError_t err = emu_prepare(*oa, akc, e.da, e.xa, e.pa, s);
     if (err != hipSuccess) return err;
   }
   if (ob) {
-    if (ob->K > EMU_MAX_K) return hipErrorInvalidValue;
-    return emu_prepare(*ob, false, e.db, e.xb, s, bt0, bt1);
+    if (ob->K > NB2) return hipErrorInvalidValue;
+    return emu_prepare(*ob, false, e.db, e.xb, e.pb, s, bt0, bt1);
   }
   return hipSuccess;
 }
@@ -569,6 +572,8 @@ GebWork geb_work(void* work, size_t bytes, int64_t n, int32_t prec, bool adjoint
       w.emu.db = cv.take<int8_t>(emu_digit_bytes(rb, NB2));
       w.emu.xa = cv.take<int>(emu_scale_count(np));
       w.emu.xb = cv.take<int>(emu_scale_count(rb));
+      w.emu.pa = cv.take<int>(emu_part_count(np, NB2));
+      w.emu.pb = cv.take<int>(emu_part_count(rb, NB2));
     }
   } else {
     w.ldy = rhs_ld(n, pad_elems<float>());
