@@ -454,73 +454,111 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline_timing(oracle, inst, f_enf, b_ref, g_host, iters: int, n1: int, n2: int) -> dict:
-    """The oracle on the host cores, one part of the step at a time on the
-    8192-face input: each part run once as a warm-up (the solve's warm-up is
-    the accuracy check run just before), then the median of three timed runs
-    (time.perf_counter).  The step is 'iters' enforcement iterations, one
-    solve, one adjoint and the two-level aggregation; one enforcement
-    iteration is timed and multiplied by the iteration count of the GPU run
-    (the whole enforcement would take about 12 minutes).  A one-thread figure
-    for scale: the solve with BLAS limited to one thread, its factorization
-    timed whole and its triangular solves on 1024 of the n + 1 right-hand
-    sides scaled to all of them (their cost is linear in the count); the
-    enforcement and aggregation parts are single-threaded NumPy in both."""
+def _submodel(f, m: int):
+    """Every (N/m)-th face of an N x (N+1) open-system matrix as an m-face
+    model (base and wall faces alike): the factors towards the faces left
+    out join the space column, so the rows stay closed."""
     import numpy as np
-    import scipy.linalg as sla
+    n = f.shape[0]
+    idx = np.arange(m) * (n // m)
+    rows = f[idx]
+    rest = np.ones(n + 1, dtype=bool)
+    rest[idx] = False
+    sub = np.empty((m, m + 1))
+    sub[:, :m] = rows[:, idx]
+    sub[:, m] = rows[:, rest].sum(axis=1)
+    return sub, idx
+
+
+def cpu_baseline_timing(oracle, inst, f_enf, b_ref, g_host, iters: int, n1: int, n2: int,
+                        m_enf: int = 4096, m_one: int = 2048) -> dict:
+    """The oracle on the host cores, one part of the 8192-face step at a time
+    (time.perf_counter):
+
+    * enforcement: one FRACVAR iteration on the m_enf-face sub-model of the
+      noisy input (every (N/m)-th face, the others merged into the space
+      column), a warm-up and the median of 3 runs, scaled by the entry count
+      N (N+1) / (m (m+1)) (the oracle's iteration is elementwise array work,
+      linear in the entries once the arrays exceed the caches: 269 ns per
+      entry at m = 4096 against 251 at the full size on the GPU machine's host,
+      while m = 2048 fits in cache at 80) and by the GPU run's iteration count;
+    * REF solve: the full-size LU solve, median of 3 (its warm-up is the
+      accuracy check run just before);
+    * adjoint: the full-size oracle adjoint, one run (11 s; three would
+      more than double the baseline's cost);
+    * aggregation 8192 -> 2048 -> 128: a warm-up and the median of 3.
+
+    A one-thread figure for scale: the solve and the adjoint with BLAS
+    limited to one thread on the m_one-face sub-model of the enforced F, a
+    warm-up and the median of 3 each, scaled by their flop counts ((2/3) N^3
+    + 2 N^2 (N+1) and (2/3) N^3 + 4 N^2 (N+1): the adjoint's dJ/dB product
+    F^T Lambda costs as much as its solve)."""
+    import numpy as np
     import threadpoolctl
     threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
     eps, rho, area = inst.eps[0], inst.rho[0], inst.area
     g1, g2 = inst.groups
+    n = f_enf.shape[0]
 
-    def med3(fn, warm=True):
+    def timed(fn, runs=3, warm=True):
         if warm:
             fn()
         ts = []
-        for _ in range(3):
+        for _ in range(runs):
             t = time.perf_counter()
             fn()
             ts.append(time.perf_counter() - t)
         return float(np.median(ts)), [float(x) for x in ts]
 
-    t_enf, r_enf = med3(lambda: oracle.enforce_vf(inst.f_noisy, area, inst.n_rays, "fracvar", tol=0.0, max_iter=1))
-    log(f"cpu baseline: enforcement iteration {t_enf:.2f} s")
-    t_sol, r_sol = med3(lambda: oracle.gebhart_ref(f_enf, eps, rho), warm=False)
+    def lu_flops(m):
+        return 2.0 / 3.0 * m ** 3 + 2.0 * m * m * (m + 1)
+
+    def adj_flops(m):
+        return 2.0 / 3.0 * m ** 3 + 4.0 * m * m * (m + 1)
+
+    me, mo = min(m_enf, n), min(m_one, n)
+    fe, ie = _submodel(inst.f_noisy, me)
+    t_e, r_e = timed(lambda: oracle.enforce_vf(fe, area[ie], inst.n_rays[ie], "fracvar", tol=0.0, max_iter=1))
+    s_enf = n * (n + 1) / (me * (me + 1))
+    t_enf = t_e * s_enf
+    log(f"cpu baseline: enforcement iteration {t_e:.2f} s on {me} faces -> {t_enf:.2f} s")
+    t_sol, r_sol = timed(lambda: oracle.gebhart_ref(f_enf, eps, rho), warm=False)
     log(f"cpu baseline: solve {t_sol:.2f} s")
-    t_adj, r_adj = med3(lambda: oracle.gebhart_ref_adjoint(f_enf, eps, rho, b_ref, g_host))
+    t_adj, r_adj = timed(lambda: oracle.gebhart_ref_adjoint(f_enf, eps, rho, b_ref, g_host), runs=1, warm=False)
     log(f"cpu baseline: adjoint {t_adj:.2f} s")
 
     def agg():
         y1, w1 = oracle.aggregate_nodes(b_ref, eps * area, g1, n1)
         oracle.aggregate_nodes(y1, w1, g2, n2)
 
-    t_agg, r_agg = med3(agg)
+    t_agg, r_agg = timed(agg)
     s_cpu = t_enf * iters + t_sol + t_adj + t_agg
-    n = f_enf.shape[0]
-    cols = min(1024, n + 1)
+    # one BLAS thread: the solve and the adjoint on the smaller sub-model
+    k1, i1 = _submodel(f_enf, mo)
+    e1, r1 = eps[i1], rho[i1]
+    g1s = np.ascontiguousarray(g_host[:mo, :mo + 1])  # any dJ/dB of the right shape
     with threadpoolctl.threadpool_limits(1):
-        k, e = oracle.form_k_e(f_enf, eps, rho)
-        t = time.perf_counter()
-        lu = sla.lu_factor(k)
-        t_f1 = time.perf_counter() - t
-        t = time.perf_counter()
-        sla.lu_solve(lu, e[:, :cols])
-        t_s1 = (time.perf_counter() - t) * (n + 1) / cols
-    del k, e, lu
-    s_one = s_cpu - t_sol + (t_f1 + t_s1)
-    log(f"cpu baseline: one-thread solve {t_f1 + t_s1:.1f} s")
+        b1 = oracle.gebhart_ref(k1, e1, r1)
+        t_s1, _ = timed(lambda: oracle.gebhart_ref(k1, e1, r1))
+        t_a1, _ = timed(lambda: oracle.gebhart_ref_adjoint(k1, e1, r1, b1, g1s))
+    t_one = t_s1 * lu_flops(n) / lu_flops(mo) + t_a1 * adj_flops(n) / adj_flops(mo)
+    s_one = s_cpu - t_sol - t_adj + t_one
+    log(f"cpu baseline: one-thread solve + adjoint {t_one:.1f} s")
     return {"value": 1.0 / s_cpu, "unit": "REF matrices/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"one step's parts on the n={n} input, each the median of 3 timed runs after a warm-up: "
-                       f"one of the {iters} enforcement iterations (scaled by {iters}), the REF solve "
-                       f"(LAPACK getrf/getrs), the adjoint and the two-level aggregation"),
+            "sample": (f"the step's parts on the n={n} input: one FRACVAR enforcement iteration on the {me}-face "
+                       f"sub-model of the noisy F (every {n // me}th face, the rest merged into space; a warm-up "
+                       f"and the median of 3, x {s_enf:.2f} entries, x {iters} iterations), the full LU solve "
+                       f"(median of 3), the full adjoint (one run), the two-level aggregation (a warm-up and the "
+                       f"median of 3)"),
             "seconds_per_step": s_cpu, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
             "parts_s": {"enforce_iteration": t_enf, "enforce_iterations": iters, "solve": t_sol, "adjoint": t_adj,
                         "aggregation": t_agg},
-            "runs_s": {"enforce_iteration": r_enf, "solve": r_sol, "adjoint": r_adj, "aggregation": r_agg},
-            "one_thread": {"value": 1.0 / s_one, "seconds_per_step": s_one, "solve_s": t_f1 + t_s1,
-                           "sample": (f"the solve with one BLAS thread: getrf timed once, getrs on {cols} of "
-                                      f"{n + 1} right-hand sides scaled by {n + 1}/{cols}; the other parts as above "
-                                      "(single-threaded NumPy)")}}
+            "runs_s": {"enforce_iteration_sample": r_e, "solve": r_sol, "adjoint": r_adj, "aggregation": r_agg},
+            "one_thread": {"value": 1.0 / s_one, "seconds_per_step": s_one, "solve_and_adjoint_s": t_one,
+                           "sample": (f"the LU solve and the adjoint with one BLAS thread on the {mo}-face "
+                                      f"sub-model of the enforced F, a warm-up and the median of 3 each, scaled "
+                                      f"by their flop counts; the enforcement and aggregation parts as above "
+                                      f"(single-threaded NumPy)")}}
 
 
 def target_n16384(rad, oracle, W, d, reps: int = 3) -> dict:
