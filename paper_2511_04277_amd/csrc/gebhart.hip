@@ -841,6 +841,7 @@ extern "C" int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf, cons
   Fact<double> f = make_fact<double>(factors, factor_layout<double>(n));
   double* Y = static_cast<double*>(w.y);
   const dim3 egrid(static_cast<unsigned>(ceil_div(n + 1, 256)), static_cast<unsigned>(n));
+  const dim3 ugrid(static_cast<unsigned>(ceil_div(n + 1, LSQ_KC)), static_cast<unsigned>(ceil_div(n, LSQ_RB)));
   hipLaunchKernelGGL(scalars_init, dim3(1), dim3(64), 0, s, w.sc);
   hipLaunchKernelGGL(lsq_mask_init, egrid, dim3(256), 0, s, F, static_cast<long>(ldf), ni,
                      (flags & RAD_LSQ_SPVA) ? 1 : 0, l.mask[0], w.sc);
@@ -849,12 +850,12 @@ extern "C" int32_t rad_enforce_lsq(const double* F, int64_t n, int64_t ldf, cons
   for (;;) {
     ++rounds;
     hipLaunchKernelGGL(fill_zero<int>, dim3(1), dim3(64), 0, s, l.negatives, 1L);
-    hipLaunchKernelGGL(lsq_schur, dim3(f.np), dim3(256), 0, s, F, static_cast<long>(ldf), ni, omega, l.mask[cur],
-                       f.kf, f.ldk, f.np, Y, w.ldy);
+    hipLaunchKernelGGL(lsq_schur, dim3(static_cast<unsigned>(ceil_div(f.np, LSQ_RB))), dim3(256), 0, s, F,
+                       static_cast<long>(ldf), ni, omega, l.mask[cur], f.kf, f.ldk, f.np, Y, w.ldy);
     RAD_HIP_CHECK(factor_forward<double>(f, Y, w.ldy, LSQ_RHS, w.sc, s, ew, static_cast<double*>(w.scr)));
     RAD_HIP_CHECK(panel_inverses<double>(f, static_cast<double*>(w.scr), w.ldt, s));
     RAD_HIP_CHECK(back_solve<double>(f, Y, w.ldy, LSQ_RHS, static_cast<double*>(w.scr), w.ldy, s, ew));
-    hipLaunchKernelGGL(lsq_update, egrid, dim3(256), 0, s, F, static_cast<long>(ldf), ni, omega, l.mask[cur], Y,
+    hipLaunchKernelGGL(lsq_update, ugrid, dim3(256), 0, s, F, static_cast<long>(ldf), ni, omega, l.mask[cur], Y,
                        w.ldy, nnr, l.mask[1 - cur], Fout, static_cast<long>(ldo), l.negatives);
     RAD_HIP_CHECK(hipGetLastError());
     RAD_HIP_CHECK(hipMemcpyAsync(&negatives, l.negatives, sizeof(int), hipMemcpyDeviceToHost, s));

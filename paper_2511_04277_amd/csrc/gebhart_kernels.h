@@ -258,101 +258,169 @@ lsq_mask_init(const double* __restrict__ F, long ldf, int n, int spva, uint8_t* 
   mask[static_cast<long>(i) * (n + 1) + k] = (spva && v == 0.0) ? 0 : 1;
 }
 
+// Both kernels below take 16 rows i per workgroup and walk the columns k in
+// chunks of 64: the rows' own entries F_ik and a_ik are read as contiguous
+// 512-byte row pieces, and the partner entries F_ki, a_ki of the chunk (64
+// rows of 16 contiguous entries each) are staged in LDS, so no access is
+// strided.  Thread t works on rows w + 4j (w = t / 64, j = 0..3) of the block
+// and column t % 64 of each chunk.
+constexpr int LSQ_RB = 16;  // rows per workgroup
+constexpr int LSQ_KC = 64;  // columns per chunk
+
+// the chunk's partner entries F_ki, a_ki (k in [k0, k0 + 64), i in the block)
+__device__ __forceinline__ void lsq_stage_partner(const double* __restrict__ F, long ldf,
+                                                  const uint8_t* __restrict__ mask, long ldm, int n, int i0, int k0,
+                                                  double (*pf)[LSQ_RB + 1], uint8_t (*pm)[LSQ_RB + 1]) {
+#pragma unroll
+  for (int q = 0; q < LSQ_KC * LSQ_RB / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int kk = e / LSQ_RB, ii = e % LSQ_RB;
+    const int k = k0 + kk, i = i0 + ii;
+    const bool in = k < n && i < n;
+    pf[kk][ii] = in ? F[static_cast<long>(k) * ldf + i] : 0.0;
+    pm[kk][ii] = in ? mask[static_cast<long>(k) * ldm + i] : 0;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 lsq_schur(const double* __restrict__ F, long ldf, int n, const double* __restrict__ W,
           const uint8_t* __restrict__ mask, double* __restrict__ KF, long ldk, int np,
           double* __restrict__ Y, long ldy) {
-  __shared__ double red[4][4];
-  const int i = blockIdx.x;
+  __shared__ double pf[LSQ_KC][LSQ_RB + 1];
+  __shared__ uint8_t pm[LSQ_KC][LSQ_RB + 1];
+  const int i0 = blockIdx.x * LSQ_RB;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const long ldm = n + 1;
-  double* krow = KF + static_cast<long>(i) * ldk;
-  double cnt = 0.0, rsum = 0.0, sub = 0.0, t = 0.0;
-  if (i < n) {
-    const double wi = W[i];
-    const double* frow = F + static_cast<long>(i) * ldf;
-    const uint8_t* mrow = mask + static_cast<long>(i) * ldm;
-    for (int k = threadIdx.x; k <= n; k += blockDim.x) {
-      const int aik = mrow[k];
-      const double fik = frow[k];
-      cnt += aik;
-      rsum += aik ? fik : 0.0;
-      double sik = 0.0;
-      if (k < n && k != i) {
-        const int aki = mask[static_cast<long>(k) * ldm + i];
-        const double wk = W[k];
-        const double d = wi * wi * aik + wk * wk * aki;
-        if (d > 0.0) {
-          const double fki = F[static_cast<long>(k) * ldf + i];
-          const double rho = (aik ? wi * fik : 0.0) - (aki ? wk * fki : 0.0);
-          if (aik) {
-            sub += wi * wi / d;
-            t += wi * rho / d;
+  double cnt[4], rsum[4], sub[4], tt[4], wi[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + w + 4 * j;
+    cnt[j] = rsum[j] = sub[j] = tt[j] = 0.0;
+    wi[j] = i < n ? W[i] : 0.0;
+  }
+  if (i0 < n) {
+    for (int k0 = 0; k0 <= n; k0 += LSQ_KC) {
+      // the rows' own entries of the chunk, loaded before the partner tile
+      // so that both sets of loads are in flight together
+      const int k = k0 + l;
+      int am[4];
+      double fv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + w + 4 * j;
+        const bool in = i < n && k <= n;
+        am[j] = in ? mask[static_cast<long>(i) * ldm + k] : 0;
+        fv[j] = in ? F[static_cast<long>(i) * ldf + k] : 0.0;
+      }
+      __syncthreads();  // the previous chunk's partner reads are done
+      lsq_stage_partner(F, ldf, mask, ldm, n, i0, k0, pf, pm);
+      __syncthreads();
+      if (k > n) continue;
+      const double wk = k < n ? W[k] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ii = w + 4 * j, i = i0 + ii;
+        if (i >= n) continue;
+        const int aik = am[j];
+        const double fik = fv[j];
+        cnt[j] += aik;
+        rsum[j] += aik ? fik : 0.0;
+        if (k < n && k != i) {
+          double sik = 0.0;
+          const int aki = pm[l][ii];
+          const double d = wi[j] * wi[j] * aik + wk * wk * aki;
+          if (d > 0.0) {
+            const double rho = (aik ? wi[j] * fik : 0.0) - (aki ? wk * pf[l][ii] : 0.0);
+            if (aik) {
+              sub[j] += wi[j] * wi[j] / d;
+              tt[j] += wi[j] * rho / d;
+            }
+            if (aik && aki) sik = wi[j] * wk / d;
           }
-          if (aik && aki) sik = wi * wk / d;
+          KF[static_cast<long>(i) * ldk + k] = sik;
         }
       }
-      if (k < n) krow[k] = sik;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    cnt += __shfl_xor(cnt, off);
-    rsum += __shfl_xor(rsum, off);
-    sub += __shfl_xor(sub, off);
-    t += __shfl_xor(t, off);
+  // row sums over the 64 lanes of the wave (fixed order)
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    for (int off = 32; off > 0; off >>= 1) {
+      cnt[j] += __shfl_xor(cnt[j], off);
+      rsum[j] += __shfl_xor(rsum[j], off);
+      sub[j] += __shfl_xor(sub[j], off);
+      tt[j] += __shfl_xor(tt[j], off);
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = i0 + w + 4 * j;
+    if (i >= np) continue;
+    double* krow = KF + static_cast<long>(i) * ldk;
+    double* yrow = Y + static_cast<long>(i) * ldy;
+    if (i < n) {
+      // the diagonal, the padding columns, and the right-hand side
+      for (long k = n + l; k < ldk; k += 64) krow[k] = 0.0;
+      if (l == 0) {
+        krow[i] = cnt[j] > 0.0 ? cnt[j] - sub[j] : 1.0;
+        yrow[0] = cnt[j] > 0.0 ? (rsum[j] - 1.0) - tt[j] : 0.0;
+      }
+      for (long c = 1 + l; c < ldy; c += 64) yrow[c] = 0.0;
+    } else {
+      // padding rows: identity
+      for (long k = l; k < ldk; k += 64) krow[k] = k == i ? 1.0 : 0.0;
+      for (long c = l; c < ldy; c += 64) yrow[c] = 0.0;
+    }
   }
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    red[wv][0] = cnt;
-    red[wv][1] = rsum;
-    red[wv][2] = sub;
-    red[wv][3] = t;
-  }
-  // padding columns (and the whole row past n): identity
-  for (long k = (i < n ? n : 0) + threadIdx.x; k < ldk; k += blockDim.x) krow[k] = (k == i && k < np) ? 1.0 : 0.0;
-  __syncthreads();
-  if (threadIdx.x == 0 && i < n) {
-    const double c = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-    const double r = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
-    const double sb = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
-    const double tt = (red[0][3] + red[1][3]) + (red[2][3] + red[3][3]);
-    krow[i] = c > 0.0 ? c - sb : 1.0;
-    Y[static_cast<long>(i) * ldy] = c > 0.0 ? (r - 1.0) - tt : 0.0;
-  }
-  double* yrow = Y + static_cast<long>(i) * ldy;
-  for (long c = (i < n ? 1 : 0) + threadIdx.x; c < ldy; c += blockDim.x) yrow[c] = 0.0;
 }
 
 // F_hat from lambda (column 0 of Y); NNR: negative active entries leave the
 // next round's mask; every entry of the mask is written (ping-pong buffers).
+// One workgroup per 16 rows x one 64-column chunk (grid: chunks x row blocks).
 __global__ void __launch_bounds__(256)
 lsq_update(const double* __restrict__ F, long ldf, int n, const double* __restrict__ W,
            const uint8_t* __restrict__ mask, const double* __restrict__ Y, long ldy, int nnr,
            uint8_t* __restrict__ mask_next, double* __restrict__ Fo, long ldo, int* __restrict__ negatives) {
-  const int i = blockIdx.y;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k > n) return;
+  __shared__ double pf[LSQ_KC][LSQ_RB + 1];
+  __shared__ uint8_t pm[LSQ_KC][LSQ_RB + 1];
+  __shared__ double yk[LSQ_KC];
+  const int k0 = blockIdx.x * LSQ_KC, i0 = blockIdx.y * LSQ_RB;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const long ldm = n + 1;
-  const int aik = mask[static_cast<long>(i) * ldm + k];
-  double v = 0.0;
-  if (aik) {
-    const double li = Y[static_cast<long>(i) * ldy];
-    const double fik = F[static_cast<long>(i) * ldf + k];
-    v = fik - li;
-    if (k < n && k != i) {
-      const int aki = mask[static_cast<long>(k) * ldm + i];
-      const double wi = W[i], wk = W[k];
-      const double d = wi * wi + wk * wk * aki;
-      const double fki = aki ? F[static_cast<long>(k) * ldf + i] : 0.0;
-      const double lk = Y[static_cast<long>(k) * ldy];
-      const double nu = ((wi * fik - wk * fki) - wi * li + (aki ? wk * lk : 0.0)) / d;
-      // a partner held at zero makes the pair's row read W_i F_ik = 0: exactly zero
-      v = aki ? v - wi * nu : 0.0;
+  lsq_stage_partner(F, ldf, mask, ldm, n, i0, k0, pf, pm);
+  if (t < LSQ_KC) yk[t] = k0 + t < n ? Y[static_cast<long>(k0 + t) * ldy] : 0.0;
+  __syncthreads();
+  const int k = k0 + l;
+  int neg_count = 0;
+  if (k <= n) {
+    const double wk = k < n ? W[k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ii = w + 4 * j, i = i0 + ii;
+      if (i >= n) continue;
+      const int aik = mask[static_cast<long>(i) * ldm + k];
+      double v = 0.0;
+      if (aik) {
+        const double li = Y[static_cast<long>(i) * ldy];
+        const double fik = F[static_cast<long>(i) * ldf + k];
+        v = fik - li;
+        if (k < n && k != i) {
+          const int aki = pm[l][ii];
+          const double wi = W[i];
+          const double d = wi * wi + wk * wk * aki;
+          const double fki = aki ? pf[l][ii] : 0.0;
+          const double nu = ((wi * fik - wk * fki) - wi * li + (aki ? wk * yk[l] : 0.0)) / d;
+          // a partner held at zero makes the pair's row read W_i F_ik = 0: exactly zero
+          v = aki ? v - wi * nu : 0.0;
+        }
+      }
+      const int neg = nnr && aik && v < 0.0;
+      neg_count += neg;
+      mask_next[static_cast<long>(i) * ldm + k] = aik && !neg;
+      Fo[static_cast<long>(i) * ldo + k] = v;
     }
   }
-  const int neg = nnr && aik && v < 0.0;
-  if (neg) atomicAdd(negatives, 1);
-  mask_next[static_cast<long>(i) * ldm + k] = aik && !neg;
-  Fo[static_cast<long>(i) * ldo + k] = v;
+  for (int off = 32; off > 0; off >>= 1) neg_count += __shfl_xor(neg_count, off);
+  if (l == 0 && neg_count > 0) atomicAdd(negatives, neg_count);
 }
 
 // P = F_sq diag(rho) in FP64, zero outside n x n (refinement residuals).
