@@ -292,7 +292,7 @@ gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __rest
     for (int q = 0; q < g.nseg; ++q) ntx += g.N[q] > 0 ? (g.N[q] + TS - 1) / TS : 0;
     int bx, by;
     grouped_tile(t - tile_start[lo], ntx, (g.M + TS - 1) / TS, TILE_GROUP, bx, by);
-    gemm_tile<T, TRANS_A, TS>(g, bx, by);
+    gemm_tile<T, TRANS_A, TS, false>(g, bx, by);
   }
 }
 
