@@ -296,8 +296,32 @@ gemm_grouped_persistent(const GemmArgs<T>* __restrict__ probs, const int* __rest
   }
 }
 
-// resident workgroups: two 128-tiles or four 64-tiles per CU
-inline unsigned persistent_grid(int ts) { return ts == GEMM_TILE ? 2 * 256 : 4 * 256; }
+// The same walk with one 64 x 64 tile per workgroup (grid = all tiles, so the
+// hardware hands them out in list order, round robin over the XCDs): without
+// the persistent loop the tile keeps its C values in registers across the K
+// loop, as the single-product kernel does.
+template <class T, bool TRANS_A>
+__global__ void __launch_bounds__(256, 4)
+gemm_grouped_tiles(const GemmArgs<T>* __restrict__ probs, const int* __restrict__ tile_start, int nprob) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const GemmArgs<T>& g = probs[lo];
+  int ntx = 0;
+  for (int q = 0; q < g.nseg; ++q) ntx += g.N[q] > 0 ? (g.N[q] + 63) / 64 : 0;
+  int bx, by;
+  grouped_tile(t - tile_start[lo], ntx, (g.M + 63) / 64, TILE_GROUP, bx, by);
+  gemm_tile<T, TRANS_A, 64, true>(g, bx, by);
+}
+
+// resident workgroups of the persistent kernel: two 128-tiles per CU; the
+// 64-tile launches take one workgroup per tile
+inline unsigned grouped_grid(int ts, int tiles) {
+  return ts == GEMM_TILE ? std::min<unsigned>(static_cast<unsigned>(tiles), 2 * 256) : static_cast<unsigned>(tiles);
+}
 
 // ------------------------------------------------------------- host side ---
 struct TableBuilder {
@@ -348,7 +372,7 @@ bool gemm_launch(TableBuilder* tb, std::vector<GemmArgs<U>>& a, bool trans, rad_
   L.count = static_cast<int>(a.size());
   L.off = tb->add(a.data(), a.size());
   L.off2 = tb->add(st.data(), st.size());
-  L.grid = std::min<unsigned>(static_cast<unsigned>(st.back()), persistent_grid(ts));
+  L.grid = grouped_grid(ts, st.back());
   a.clear();
   return true;
 }
@@ -905,10 +929,9 @@ hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const cha
                              L.count);
       } else {
         if (L.trans)
-          hipLaunchKernelGGL((gemm_grouped_persistent<T, true, 64>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
+          hipLaunchKernelGGL((gemm_grouped_tiles<T, true>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
         else
-          hipLaunchKernelGGL((gemm_grouped_persistent<T, false, 64>), dim3(L.grid), dim3(256), 0, s, a, ts,
-                             L.count);
+          hipLaunchKernelGGL((gemm_grouped_tiles<T, false>), dim3(L.grid), dim3(256), 0, s, a, ts, L.count);
       }
     }
   }
