@@ -459,7 +459,7 @@ struct Sched {
     L.count = static_cast<int>(g.size());
     L.off = tb->add(g.data(), g.size());
     L.off2 = tb->add(st.data(), st.size());
-    L.grid = std::min<unsigned>(static_cast<unsigned>(st.back()), 2 * 256);
+    L.grid = static_cast<unsigned>(st.back());  // one workgroup per tile
     L.flops = f;
     L.bytes = b;
     if (st.back() > 0) out.push_back(L);
@@ -901,7 +901,7 @@ hipError_t run_launches(const std::vector<rad_batch_plan::Launch>& ls, const cha
         hipLaunchKernelGGL(b_emu_split<false>, dim3(L.grid), dim3(256), 0, s, jobs, st, L.count);
     } else if (L.kind == L_EMU_GEMM) {
       ProfScope prof(s, RAD_PROF_GEMM_I8X, L.flops, L.bytes);
-      hipLaunchKernelGGL(emu_gemm_grouped<EMU_S>, dim3(L.grid), dim3(EMU_THREADS), 0, s,
+      hipLaunchKernelGGL(emu_gemm_grouped_tiles<EMU_S>, dim3(L.grid), dim3(EMU_THREADS), 0, s,
                          reinterpret_cast<const EmuGemmArgs*>(tables + L.off),
                          reinterpret_cast<const int*>(tables + L.off2), L.count);
     } else if (L.kind == L_COPY) {

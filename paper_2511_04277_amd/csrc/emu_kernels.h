@@ -207,10 +207,8 @@ struct EmuGemmArgs {
 // receives the tile's C block and its row and column scale exponents (tiles
 // that lie whole inside one column segment), so the epilogue does not wait
 // on global loads: 14-17 % faster on K = 1024 products than loading C in
-// the epilogue, bitwise the same results (CPRE; the persistent grouped
-// kernel keeps the plain epilogue, where the staging's registers would spill
-// in its tile loop).
-template <int S, bool CPRE>
+// the epilogue, bitwise the same results.
+template <int S>
 __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int by,
                                               emu_v4i (*lds)[S * EMU_TILE * 4]) {
   constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
@@ -240,8 +238,8 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
   const int row0t = by * EMU_TILE, col0t = bx * EMU_TILE;
   const int seg0 = (g.nseg > 1 && col0t >= g.N[0]) ? 1 : 0;
   const int cc0 = col0t - (seg0 ? g.N[0] : 0);
-  const bool cpre = CPRE && __builtin_amdgcn_readfirstlane(row0t + EMU_TILE <= g.M && seg0 < g.nseg &&
-                                                           cc0 + EMU_TILE <= g.N[seg0]);
+  const bool cpre =
+      __builtin_amdgcn_readfirstlane(row0t + EMU_TILE <= g.M && seg0 < g.nseg && cc0 + EMU_TILE <= g.N[seg0]);
   double* cl = reinterpret_cast<double*>(&lds[0][0]);
   int* xl = reinterpret_cast<int*>(cl + EMU_TILE * EMU_TILE);
   auto stage_c = [&]() {
@@ -327,7 +325,6 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
           Cb[static_cast<long>(rr) * ldc + 16 * j + fr] = fma(g.alpha, ldexp(x, ea + eb), c0);
         }
     }
-    __syncthreads();  // the C block has been read: a persistent workgroup may refill the LDS
     return;
   }
 #pragma unroll
@@ -364,29 +361,27 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm(EmuGemmArgs g) {
   __shared__ emu_v4i lds[2][S * EMU_TILE * 4];  // [A, B][chunk]
   int bx, by;
   grouped_tile(xcd_contiguous(blockIdx.x, g.ntx * g.nty), g.ntx, g.nty, TILE_GROUP, bx, by);
-  emu_gemm_tile<S, true>(g, bx + g.tx0, by + g.ty0, lds);
+  emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
 }
 
-// Many products in one persistent launch (the batched solves): workgroups
-// walk the concatenated tile list (prefix sums in tile_start) in list order.
-// A workgroup starts its next tile's copies only after every wave has read
-// the last k block of the previous tile (the barrier after the fragment reads).
+// Many products in one launch with one workgroup per tile (grid = the
+// concatenated tile list, handed out in list order): each tile stages its C
+// block in LDS as emu_gemm does.
 template <int S>
-__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm_grouped(const EmuGemmArgs* __restrict__ probs,
-                                                                   const int* __restrict__ tile_start, int nprob) {
+__global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm_grouped_tiles(const EmuGemmArgs* __restrict__ probs,
+                                                                         const int* __restrict__ tile_start,
+                                                                         int nprob) {
   __shared__ emu_v4i lds[2][S * EMU_TILE * 4];
-  const int total = tile_start[nprob];
-  for (int b = blockIdx.x; b < total; b += gridDim.x) {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    const EmuGemmArgs& g = probs[lo];
-    int bx, by;
-    grouped_tile(b - tile_start[lo], g.ntx, g.nty, TILE_GROUP, bx, by);
-    emu_gemm_tile<S, false>(g, bx + g.tx0, by + g.ty0, lds);
+  const int b = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
   }
+  const EmuGemmArgs& g = probs[lo];
+  int bx, by;
+  grouped_tile(b - tile_start[lo], g.ntx, g.nty, TILE_GROUP, bx, by);
+  emu_gemm_tile<S>(g, bx + g.tx0, by + g.ty0, lds);
 }
 
 // ---- host side ------------------------------------------------------------
