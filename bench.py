@@ -95,17 +95,15 @@ def kernel_source_hash(sources) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kname: str, prec: str):
-    """HBM bytes per launch of the GEMM from the committed counter summary.
+EXECUTED = {
+    "emu_gemm<7>": (os.path.join(ROOT, "profiles", "emu_gemm_open_box_n8192_mfma.txt"),
+                    [os.path.join(_CSRC, "emu_kernels.h")]),
+}
 
-    The summary records FETCH_SIZE and WRITE_SIZE averages per dispatch,
-    scaled by the same counters on a plain copy of known size, together with
-    the hash of the kernel source they were taken on; a changed kernel gives
-    None (counters are stale).
-    """
-    if kname not in TRAFFIC:
-        return None
-    path, sources = TRAFFIC[kname]
+
+def _counter_summary(path, sources, kname):
+    """key = value lines of a committed counter summary, or None when it is
+    missing or was taken on another version of the kernel source."""
     if not os.path.exists(path):
         return None
     vals = {}
@@ -116,7 +114,31 @@ def measured_traffic(kname: str, prec: str):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash(sources) or vals.get("kernel") != kname:
         return None
-    return float(vals["hbm_bytes_per_launch"])
+    return vals
+
+
+def executed_fraction(kname: str):
+    """Share of the dense digit work that the emulated GEMM executes in the
+    step (tiles with all-zero operand rows or columns are skipped), from the
+    committed MFMA-counter summary; None when it is stale."""
+    if kname not in EXECUTED:
+        return None
+    vals = _counter_summary(*EXECUTED[kname], kname)
+    return float(vals["executed_fraction"]) if vals else None
+
+
+def measured_traffic(kname: str, prec: str):
+    """HBM bytes per launch of the GEMM from the committed counter summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE averages per dispatch,
+    scaled by the same counters on a plain copy of known size, together with
+    the hash of the kernel source they were taken on; a changed kernel gives
+    None (counters are stale).
+    """
+    if kname not in TRAFFIC:
+        return None
+    vals = _counter_summary(*TRAFFIC[kname], kname)
+    return float(vals["hbm_bytes_per_launch"]) if vals else None
 
 
 def main() -> int:
@@ -354,7 +376,21 @@ def main() -> int:
     extra = {}
     if dom == "gemm_i8x":
         peak, kname, executes = PEAK_TFLOPS["int8"], "emu_gemm<7>", "int8 MFMA (digit products)"
-        # the int8 work actually issued: 28 digit products per FP64 product
+        # Tiles whose operand rows or columns are all zero are skipped, so the
+        # kernel executes only part of the dense 2 M N K; achieved counts the
+        # executed part (the FP64 products of the tiles that ran, by the MFMA
+        # counters' share of the dense digit work), the dense rate is reported
+        # beside it.  Stale counters: achieved stays dense and says so.
+        dense = achieved
+        ex = executed_fraction(kname)
+        extra["dense_fp64_equivalent_tflops"] = dense
+        extra["executed_fraction"] = ex
+        if ex is not None:
+            achieved = dense * ex
+            extra["achieved_counts"] = "executed tiles (MFMA counters' share of the dense work)"
+        else:
+            extra["achieved_counts"] = "dense 2 M N K (the counter summary is stale)"
+        # the int8 work issued: 28 digit products per executed FP64 product
         extra["int8_tops_issued"] = achieved * I8X_PRODUCTS
         extra["mfma_issue_frac"] = achieved * I8X_PRODUCTS / PEAK_TFLOPS["int8"]
         extra["fp64_equivalent_frac_of_fp64_peak"] = achieved / PEAK_TFLOPS["fp64"]
