@@ -582,7 +582,7 @@ def cpu_baseline_timing(oracle, inst, f_enf, b_ref, g_host, iters: int, n1: int,
     log(f"cpu baseline: one-thread solve + adjoint {t_one:.1f} s")
     return {"value": 1.0 / s_cpu, "unit": "REF matrices/s", "cores": int(threads), "kind": "oracle",
             "sample": (f"the step's parts on the n={n} input: one FRACVAR enforcement iteration on the {me}-face "
-                       f"sub-model of the noisy F (every {n // me}th face, the rest merged into space; a warm-up "
+                       f"sub-model of the noisy F (one face in {n // me}, the rest merged into space; a warm-up "
                        f"and the median of 3, x {s_enf:.2f} entries, x {iters} iterations), the full LU solve "
                        f"(median of 3), the full adjoint (one run), the two-level aggregation (a warm-up and the "
                        f"median of 3)"),
