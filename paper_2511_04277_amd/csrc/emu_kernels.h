@@ -293,19 +293,16 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
           for (int j = 0; j < 2; ++j)
             ci[s + u][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[s][i], bf[u][j], ci[s + u][i][j], 0, 0, 0);
   };
-  stage(0);
   // A tile whose operand rows (or columns) all have zero scale exponents
   // (all-zero rows of A, columns of B: coplanar faces see each other with
   // zero view factor, so whole 64 x 64 blocks of the factors and right-hand
-  // sides are zero) adds nothing to C; every wave finds the same answer while
-  // the first copies are in flight, waits for them and leaves.
+  // sides are zero) adds nothing to C; every wave finds the same answer and
+  // leaves before copying anything.
   {
     const int ea = g.xa[row0t + l], eb = g.xb[col0t + l];
-    if (__all(ea == EMU_EXP_NONE) || __all(eb == EMU_EXP_NONE)) {
-      __builtin_amdgcn_s_waitcnt(0);
-      return;
-    }
+    if (__all(ea == EMU_EXP_NONE) || __all(eb == EMU_EXP_NONE)) return;
   }
+  stage(0);
   // the last block is peeled so that the C staging's addresses are not held
   // across the loop
   for (int kb = 0; kb + 1 < g.nkb; ++kb) block([&] { stage(kb + 1); });
