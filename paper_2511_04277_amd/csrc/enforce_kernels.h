@@ -41,6 +41,7 @@ struct EnfInst {
 };
 
 constexpr int ERW = ET / ENW;  // tile rows per wave
+static_assert(2 + 2 * ENW <= ET, "the row partials and maxima reuse rows of the tile buffer");
 
 // Element col of a row whose base pointer is wave-uniform: the byte offset
 // is a 32-bit lane value, so loads and stores take the scalar-base form and
@@ -99,7 +100,7 @@ __device__ __forceinline__ double kappa_c(double fij, double fji, double ci, dou
 // EDGE: the tile pair crosses n (clamped loads, masked stores).
 template <bool DIAG, bool EDGE, bool HALF>
 __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int I, int J, int first,
-                                               double (*sB)[ETP], double (*red)[ET], double (*rowc)[ET]) {
+                                               double (*sB)[ETP], double (*rowc)[ET]) {
 #pragma clang fp contract(off)
   double* __restrict__ F = in.F;
   const long ldf = in.ldf;
@@ -235,7 +236,6 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
   // own tile transposed into LDS, then each thread sums ERW entries of row l
 #pragma unroll
   for (int k = 0; k < ERW; ++k) sB[l][w + ENW * k] = a[k];
-  red[w][l] = sb;  // partner row l: this wave's ERW entries
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_xor(rmax, off));
     emax = fmax(emax, __shfl_xor(emax, off));
@@ -245,7 +245,11 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
 #pragma unroll
   for (int k = 0; k < ERW; ++k) sa += sB[w + ENW * k][l];
   __syncthreads();
-  red[ENW + w][l] = sa;  // own row l: this wave's ERW entries
+  // the transposed tile has been summed: LDS rows 2.. take this wave's
+  // partial sums of the partner's row l and of the own row l, rows 0 and 1
+  // the wave maxima
+  sB[2 + w][l] = sb;
+  sB[2 + ENW + w][l] = sa;
   if (l == 0) {
     sB[0][w] = rmax;
     sB[1][w] = emax;
@@ -255,8 +259,8 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
     double s_own = 0.0, s_par = 0.0;
 #pragma unroll
     for (int q = 0; q < ENW; ++q) {
-      s_own += red[ENW + q][l];
-      s_par += red[q][l];
+      s_own += sB[2 + ENW + q][l];
+      s_par += sB[2 + q][l];
     }
     const int t = in.t;
     double* __restrict__ partial = in.partial;
@@ -286,7 +290,6 @@ __device__ __forceinline__ void enf_sweep_tile(const EnfInst& in, long pair, int
 __device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int first) {
   if (in.ctrl->converged || in.ctrl->status < 0) return;
   __shared__ double sB[ET][ETP];
-  __shared__ double red[2 * (ENW)][ET];  // per-wave row partials: partner, own
   __shared__ double rowc[8][ET];  // per-row constants of the own and the partner tile
   int I, J;
   pair_from_index(pair, in.t, I, J);
@@ -295,19 +298,19 @@ __device__ __forceinline__ void enf_sweep_body(const EnfInst& in, long pair, int
   const bool edge = (I + 1) * ET > in.n || (J + 1) * ET > in.n;
   if (in.mode == RAD_KAPPA_HALF) {
     if (I == J) {
-      if (edge) enf_sweep_tile<true, true, true>(in, pair, I, J, first, sB, red, rowc);
-      else enf_sweep_tile<true, false, true>(in, pair, I, J, first, sB, red, rowc);
+      if (edge) enf_sweep_tile<true, true, true>(in, pair, I, J, first, sB, rowc);
+      else enf_sweep_tile<true, false, true>(in, pair, I, J, first, sB, rowc);
     } else {
-      if (edge) enf_sweep_tile<false, true, true>(in, pair, I, J, first, sB, red, rowc);
-      else enf_sweep_tile<false, false, true>(in, pair, I, J, first, sB, red, rowc);
+      if (edge) enf_sweep_tile<false, true, true>(in, pair, I, J, first, sB, rowc);
+      else enf_sweep_tile<false, false, true>(in, pair, I, J, first, sB, rowc);
     }
   } else {
     if (I == J) {
-      if (edge) enf_sweep_tile<true, true, false>(in, pair, I, J, first, sB, red, rowc);
-      else enf_sweep_tile<true, false, false>(in, pair, I, J, first, sB, red, rowc);
+      if (edge) enf_sweep_tile<true, true, false>(in, pair, I, J, first, sB, rowc);
+      else enf_sweep_tile<true, false, false>(in, pair, I, J, first, sB, rowc);
     } else {
-      if (edge) enf_sweep_tile<false, true, false>(in, pair, I, J, first, sB, red, rowc);
-      else enf_sweep_tile<false, false, false>(in, pair, I, J, first, sB, red, rowc);
+      if (edge) enf_sweep_tile<false, true, false>(in, pair, I, J, first, sB, rowc);
+      else enf_sweep_tile<false, false, false>(in, pair, I, J, first, sB, rowc);
     }
   }
 }
