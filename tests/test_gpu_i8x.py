@@ -118,3 +118,28 @@ def test_ref_checks_and_fp64_agreement():
     d = torch.max(torch.abs(b8 - b64)).item()
     print(f"[i8x] closure={chk[0]:.2e} reciprocity={chk[1]:.2e} max|B_i8 - B_64|={d:.2e}", flush=True)
     assert d <= TOL and chk[0] < 1e-10 and chk[1] < 1e-13
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_block_sparse_plate_pairs_match_oracle(kind):
+    """Two plates (parallel or perpendicular) of about 1150 faces each: the
+    faces of one plate see each other with zero view factor, so whole 64 x 64
+    blocks of K, of its factors and of the right-hand sides are zero and the
+    emulated products skip those tiles (zero row or column exponents), next
+    to full tiles and tiles cut by the 1024-wide panels.  B against the
+    oracle, and against the FP64 path on the same input."""
+    need_gpu()
+    import paper_2511_04277_amd as rad
+    model = W._mesh_plates(kind, 1.0, 0.6, 2300)
+    inst = W._finish(f"plates{kind}", model, 10_000, W.rng_for(300, kind), 0.1, 0.9)
+    n = inst.n
+    eps, rho = inst.eps[0], inst.rho[0]
+    f = inst.f_noisy
+    assert n > 2048 and np.all(f[: n // 4, : n // 4] == 0.0)  # a coplanar block
+    print(f"[i8x] plates kind={kind} n={n}", flush=True)
+    bi, _, _ = rad.gebhart_ref(dev(f), dev(eps), dev(rho), precision="fp64_i8")
+    bf, _, _ = rad.gebhart_ref(dev(f), dev(eps), dev(rho), precision="fp64")
+    ref = oracle.gebhart_ref(f, eps, rho)
+    bi, bf = host(bi), host(bf)
+    assert np.abs(bi - ref).max() <= TOL
+    assert np.abs(bi - bf).max() <= TOL
