@@ -41,7 +41,8 @@ struct rad_batch_plan {
   // launch schedule (table offsets relative to the tables block)
   struct Launch { int kind; int trans; int ts; unsigned grid; size_t off, off2; int count; double flops, bytes; };
   std::vector<Launch> factor, back, fwd, resid;
-  size_t off_enf = 0, off_pair = 0, off_fblk = 0, off_fin = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
+  size_t off_enf = 0, off_fblk = 0, off_row = 0, off_pd = 0, off_nprow = 0, off_nrow = 0;
+  size_t off_pair_map = 0, off_fin_map = 0;
   double sweep_bytes = 0.0;  // algorithmic bytes of one sweep over every instance
   long total_pairs = 0, total_fblk = 0, total_fin = 0, total_rows = 0, total_nprow = 0, total_nrow = 0;
 };
@@ -830,9 +831,19 @@ void build_tables(rad_batch_plan* P, char* base, TableBuilder& tb) {
   P->total_fin = fin_start.back();
   P->total_rows = row_start.back();
   P->off_enf = tb.add(ei.data(), ei.size());
-  P->off_pair = tb.add(pair_start.data(), pair_start.size());
+  {
+    // block maps of the batched sweep (tile pairs) and finalize (row blocks)
+    std::vector<EnfBlk> pm, fm;
+    pm.reserve(static_cast<size_t>(P->total_pairs));
+    fm.reserve(static_cast<size_t>(P->total_fin));
+    for (int i = 0; i < P->count; ++i) {
+      for (long b = 0; b < pair_start[i + 1] - pair_start[i]; ++b) pm.push_back(EnfBlk{i, static_cast<int>(b)});
+      for (long b = 0; b < fin_start[i + 1] - fin_start[i]; ++b) fm.push_back(EnfBlk{i, static_cast<int>(b)});
+    }
+    P->off_pair_map = tb.add(pm.data(), pm.size());
+    P->off_fin_map = tb.add(fm.data(), fm.size());
+  }
   P->off_fblk = tb.add(fblk_start.data(), fblk_start.size());
-  P->off_fin = tb.add(fin_start.data(), fin_start.size());
   P->off_row = tb.add(row_start.data(), row_start.size());
   // solve problems
   std::vector<ProbDesc> pd;
@@ -1009,9 +1020,9 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
   hipStream_t s = static_cast<hipStream_t>(stream);
   const char* tables = static_cast<const char*>(work) + P->tables_off;
   const EnfInst* ei = reinterpret_cast<const EnfInst*>(tables + P->off_enf);
-  const long* pair_start = reinterpret_cast<const long*>(tables + P->off_pair);
   const long* fblk_start = reinterpret_cast<const long*>(tables + P->off_fblk);
-  const long* fin_start = reinterpret_cast<const long*>(tables + P->off_fin);
+  const EnfBlk* pair_map = reinterpret_cast<const EnfBlk*>(tables + P->off_pair_map);
+  const EnfBlk* fin_map = reinterpret_cast<const EnfBlk*>(tables + P->off_fin_map);
   const long* row_start = reinterpret_cast<const long*>(tables + P->off_row);
   const ProbDesc* pd = reinterpret_cast<const ProbDesc*>(tables + P->off_pd);
   const long* nprow = reinterpret_cast<const long*>(tables + P->off_nprow);
@@ -1027,10 +1038,10 @@ extern "C" int32_t rad_batch_run(const rad_batch_plan* P, void* work, double enf
       {
         ProfScope prof(s, RAD_PROF_ENFORCE_SWEEP, 0.0, P->sweep_bytes);
         hipLaunchKernelGGL(enf_sweep_batched, dim3(static_cast<unsigned>(P->total_pairs)), dim3(ENF_THREADS), 0, s,
-                           ei, pair_start, C, it == 0 ? 1 : 0);
+                           ei, pair_map, it == 0 ? 1 : 0);
       }
       hipLaunchKernelGGL(enf_finalize_batched, dim3(static_cast<unsigned>(P->total_fin)), dim3(256), 0, s, ei,
-                         fin_start, C, enforce_tol);
+                         fin_map, enforce_tol);
     }
     hipLaunchKernelGGL(enf_apply_scale_batched, dim3(static_cast<unsigned>(P->total_rows)), dim3(256), 0, s, ei,
                        row_start, C);

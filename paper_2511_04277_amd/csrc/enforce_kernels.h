@@ -332,11 +332,18 @@ __device__ __forceinline__ int find_segment(const long* __restrict__ start, int 
   return lo;
 }
 
-// all instances of a batch in one grid: blocks [pair_start[k], pair_start[k+1]) are instance k
+// Block map of a batched grid: block b works for instance inst on its local
+// block local (one load per block instead of a binary search over the
+// instance offsets, whose dependent loads delayed every block's start).
+struct EnfBlk {
+  int inst, local;
+};
+
+// all instances of a batch in one grid: map[b] names the instance and its tile pair
 __global__ void __launch_bounds__(ENF_THREADS, 6)
-enf_sweep_batched(const EnfInst* __restrict__ ins, const long* __restrict__ pair_start, int count, int first) {
-  const int k = find_segment(pair_start, count, blockIdx.x);
-  enf_sweep_body(ins[k], blockIdx.x - pair_start[k], first);
+enf_sweep_batched(const EnfInst* __restrict__ ins, const EnfBlk* __restrict__ map, int first) {
+  const EnfBlk m = map[blockIdx.x];
+  enf_sweep_body(ins[m.inst], m.local, first);
 }
 
 // finalize blocks (FIN_ROWS rows each), declared ahead of the decide step
@@ -471,12 +478,12 @@ __global__ void __launch_bounds__(256) enf_finalize(EnfInst in, double tol) {
   enf_finalize_body(in, blockIdx.x, gridDim.x, tol);
 }
 
-// blocks [blk_start[k], blk_start[k+1]) are the FIN_ROWS-row blocks of instance k
+// map[b]: the instance and FIN_ROWS-row block of block b
 __global__ void __launch_bounds__(256)
-enf_finalize_batched(const EnfInst* __restrict__ ins, const long* __restrict__ blk_start, int count, double tol) {
-  const int k = find_segment(blk_start, count, blockIdx.x);
-  const int nb = static_cast<int>(blk_start[k + 1] - blk_start[k]);
-  enf_finalize_body(ins[k], static_cast<int>(blockIdx.x - blk_start[k]), nb, tol);
+enf_finalize_batched(const EnfInst* __restrict__ ins, const EnfBlk* __restrict__ map, double tol) {
+  const EnfBlk m = map[blockIdx.x];
+  const EnfInst& in = ins[m.inst];
+  enf_finalize_body(in, m.local, (in.n + FIN_ROWS - 1) / FIN_ROWS, tol);
 }
 
 
