@@ -19,7 +19,7 @@
 #include <cstring>
 #include <vector>
 
-#include "emu_kernels.h"
+#include "emu_split.h"
 #include "enforce_kernels.h"
 #include "gebhart_kernels.h"
 
@@ -73,14 +73,13 @@ b_emu_rowexp_kc(const EmuJob* __restrict__ jobs, const long* __restrict__ start,
   emu_rowexp_kc_body(j.op, 0, j.T * EMU_TILE, j.ex, static_cast<int>(blockIdx.x - start[q]));
 }
 
-// scale exponents, rows contiguous: 256 rows x one k block per block
+// scale exponents, rows contiguous: one 64-row tile x one k block per block
 __global__ void __launch_bounds__(256)
 b_emu_rowexp_rc(const EmuJob* __restrict__ jobs, const long* __restrict__ start, int count) {
   const int q = find_segment(start, count, blockIdx.x);
   const EmuJob& j = jobs[q];
-  const int nbx = (j.T * EMU_TILE + 255) / 256;
   const int b = static_cast<int>(blockIdx.x - start[q]);
-  emu_rowexp_rc_body(j.op, 0, j.T * EMU_TILE, j.part, static_cast<long>(j.T) * EMU_TILE, b % nbx, b / nbx);
+  emu_rowexp_rc_body(j.op, b % j.T, b / j.T, j.part, static_cast<long>(j.T) * EMU_TILE);
 }
 
 // digits: one 64-row x 64-k block per block
@@ -433,7 +432,7 @@ struct Sched {
       double elems = 0.0;
       for (const EmuJob& j : jobs) {
         const long rows = static_cast<long>(j.T) * EMU_TILE;
-        s_exp.push_back(s_exp.back() + (kind == 0 ? (rows + 3) / 4 : (rows + 255) / 256 * j.nkb));
+        s_exp.push_back(s_exp.back() + (kind == 0 ? (rows + 3) / 4 : static_cast<long>(j.T) * j.nkb));
         s_split.push_back(s_split.back() + static_cast<long>(j.T) * j.nkb);
         elems += static_cast<double>(j.op.R) * j.op.K;
       }

@@ -22,7 +22,7 @@
 // practice (errors of random sign) about 2^-49 sqrt(K) of the row and column
 // maxima.
 //
-// Digit layout (written by emu_split, read by emu_gemm): operand rows padded
+// Digit layout (written by emu_split in emu_split.h, read by emu_gemm): operand rows padded
 // to a multiple of 64 (T tiles) and k to 64 nkb.  The 64 rows x S slices x
 // 64 k of k block kb of row tile rt are block kb T + rt, S * 256 chunks of 16
 // bytes, laid out exactly as the GEMM keeps them in LDS: chunk c
@@ -48,135 +48,12 @@ constexpr int EMU_EXP_NONE = -2000;  // scale exponent of an all-zero row
 
 typedef int emu_v4i __attribute__((ext_vector_type(4)));
 
-// ---- operand scaling and splitting -------------------------------------
-
 // LDS position of 16-byte chunk c of row r of slice s in a 64-row block.
 // The chunk index is XOR-swizzled with row bits so that the 16 (or 8) lanes
 // of one ds_read_b128 phase, which read rows r..r+15 at one chunk, hit
 // distinct banks.
 __device__ __forceinline__ int emu_lds_idx(int s, int r, int c) {
   return ((s * EMU_TILE + r) << 2) + (c ^ (((r >> 1) ^ (r >> 2)) & 3));
-}
-
-// Operand access: row r < R0 is element (r, k) at X[0][r sr[0] + k sk[0]],
-// row R0 <= r < R at X[1][(r - R0) sr[1] + k sk[1]]; both segments have the
-// same orientation (k contiguous, or rows contiguous).  Rows r >= R and
-// k >= K of the padded range read as zero.
-struct EmuOperand {
-  const double* X[2];
-  long sr[2], sk[2];
-  int R0, R, K;
-};
-
-__device__ __forceinline__ double emu_load(const EmuOperand& op, int r, int k) {
-  if (r >= op.R || k >= op.K) return 0.0;
-  const int q = r >= op.R0;
-  const long rr = r - (q ? op.R0 : 0);
-  return op.X[q][rr * op.sr[q] + static_cast<long>(k) * op.sk[q]];
-}
-
-// Scale exponents e_r (max_k |X_rk| < 2^e_r; EMU_EXP_NONE for a zero row) of
-// rows [r0, r1).  k-contiguous rows: one wave per row.
-__device__ __forceinline__ void emu_rowexp_kc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ ex,
-                                                   int blk) {
-  const int r = r0 + blk * 4 + (threadIdx.x >> 6);
-  const int l = threadIdx.x & 63;
-  if (r >= r1) return;
-  double m = 0.0;
-  for (int k = l; k < op.K; k += 64) m = fmax(m, fabs(emu_load(op, r, k)));
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  int e = 0;
-  if (m > 0.0) frexp(m, &e);  // m = f 2^e, f in [0.5, 1): m < 2^e
-  if (l == 0) ex[r] = m > 0.0 ? e : EMU_EXP_NONE;
-}
-
-static __global__ __launch_bounds__(256) void emu_rowexp_kc(EmuOperand op, int r0, int r1, int* __restrict__ ex) {
-  emu_rowexp_kc_body(op, r0, r1, ex, blockIdx.x);
-}
-
-// Rows contiguous in memory: a workgroup takes 256 rows x 64 k (each thread
-// one row, every load instruction 512 contiguous bytes) and stores the
-// exponent of each row's k block kb = by in part[kb Rp + r] (Rp: the
-// operand's padded row count); the digit pass takes the maximum over the
-// k blocks, so no atomics and no initial fill are needed.
-__device__ __forceinline__ void emu_rowexp_rc_body(const EmuOperand& op, int r0, int r1, int* __restrict__ part,
-                                                   long Rp, int bx, int by) {
-  const int r = r0 + bx * 256 + threadIdx.x;
-  const int k0 = by * EMU_KB;
-  if (r >= r1) return;
-  double m = 0.0;
-#pragma unroll 8
-  for (int k = k0; k < k0 + EMU_KB; ++k) m = fmax(m, fabs(emu_load(op, r, k)));
-  int e = EMU_EXP_NONE;
-  if (m > 0.0) frexp(m, &e);
-  part[by * Rp + r] = e;
-}
-
-static __global__ __launch_bounds__(256) void emu_rowexp_rc(EmuOperand op, int r0, int r1, int* __restrict__ part,
-                                                            long Rp) {
-  emu_rowexp_rc_body(op, r0, r1, part, Rp, blockIdx.x, blockIdx.y);
-}
-
-// Digits of one 64-row x 64-k block per workgroup (row tile rt0 + blockIdx.x
-// of T).  The block's doubles are read with 512-byte contiguous loads in
-// whichever orientation the operand has and transposed through LDS; thread t
-// forms the S digits of 16 consecutive k of row t / 4 (chunk c = t % 4), and a
-// wave's stores of one slice are one contiguous 1 KB piece of the block.
-// k-contiguous operands read their exponents from ex; rows-contiguous ones
-// take the maximum of the nkb per-k-block exponents in part (layout of
-// emu_rowexp_rc, Rp = 64 T), and the workgroups of k block 0 store it in ex
-// for the product.
-template <int S, bool KC>
-__device__ __forceinline__ void emu_split_body(const EmuOperand& op, int T, int rt, int kb, int* __restrict__ ex,
-                                               const int* __restrict__ part, int nkb, int8_t* __restrict__ out,
-                                               double (*tile)[EMU_KB + 1]) {
-  const int t = threadIdx.x;
-  const int r0 = rt * EMU_TILE, k0 = kb * EMU_KB;
-#pragma unroll
-  for (int it = 0; it < EMU_TILE * EMU_KB / 256; ++it) {
-    const int e = it * 256 + t;
-    const int row = KC ? e / EMU_KB : e % EMU_TILE;
-    const int k = KC ? e % EMU_KB : e / EMU_TILE;
-    tile[row][k] = emu_load(op, r0 + row, k0 + k);
-  }
-  const int row = t >> 2, c = t & 3;
-  int e;
-  if (KC) {
-    e = ex[r0 + row];
-  } else {
-    const long Rp = static_cast<long>(T) * EMU_TILE;
-    e = EMU_EXP_NONE;
-    for (int q = 0; q < nkb; ++q) e = max(e, part[q * Rp + r0 + row]);
-    if (kb == 0 && c == 0) ex[r0 + row] = e;
-  }
-  __syncthreads();
-  const int es = e == EMU_EXP_NONE ? 0 : e;
-  union {
-    emu_v4i v;
-    int8_t b[16];
-  } dg[S];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    double a = ldexp(tile[row][c * 16 + i], -es);  // exact
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      a *= 128.0;
-      const double d = __builtin_trunc(a);
-      a -= d;
-      dg[s].b[i] = static_cast<int8_t>(static_cast<int>(d));
-    }
-  }
-  emu_v4i* blk = reinterpret_cast<emu_v4i*>(out) + (static_cast<long>(kb) * T + rt) * S * 256;
-#pragma unroll
-  for (int s = 0; s < S; ++s) blk[emu_lds_idx(s, row, c)] = dg[s].v;
-}
-
-template <int S, bool KC>
-__global__ __launch_bounds__(256) void emu_split(EmuOperand op, int T, int rt0, int* __restrict__ ex,
-                                                 const int* __restrict__ part, int8_t* __restrict__ out) {
-  __shared__ double tile[EMU_TILE][EMU_KB + 1];
-  emu_split_body<S, KC>(op, T, rt0 + blockIdx.x, blockIdx.y, ex, part, gridDim.y, out, tile);
 }
 
 // ---- the product --------------------------------------------------------
@@ -394,46 +271,6 @@ __global__ __launch_bounds__(EMU_THREADS, 2) void emu_gemm_grouped_tiles(const E
 }
 
 // ---- host side ------------------------------------------------------------
-
-// Bytes of the digits of an operand with R rows and K columns.
-inline size_t emu_digit_bytes(long R, long K) {
-  return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE * ((K + EMU_KB - 1) / EMU_KB) * EMU_KB * EMU_S;
-}
-
-// Scale exponents and digits of the row tiles [t0, t1) of one operand (kc: k
-// contiguous in memory, else rows; t1 < 0: up to the last tile).  ex receives
-// one exponent per padded row; the digits land where the whole operand's
-// layout puts them, so disjoint tile ranges may be prepared by separate calls.
-// A rows-contiguous operand needs part, emu_part_count(R, K) ints of scratch
-// (per-k-block exponents).
-inline hipError_t emu_prepare(const EmuOperand& op, bool kc, int8_t* dig, int* ex, int* part, hipStream_t s,
-                              int t0 = 0, int t1 = -1) {
-  const int T = (op.R + EMU_TILE - 1) / EMU_TILE;
-  const int nkb = (op.K + EMU_KB - 1) / EMU_KB;
-  if (t1 < 0 || t1 > T) t1 = T;
-  if (t0 >= t1 || nkb == 0) return hipSuccess;
-  const int r0 = t0 * EMU_TILE, r1 = t1 * EMU_TILE, nr = r1 - r0;
-  if (kc) {
-    hipLaunchKernelGGL(emu_rowexp_kc, dim3((nr + 3) / 4), dim3(256), 0, s, op, r0, r1, ex);
-    hipLaunchKernelGGL((emu_split<EMU_S, true>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex,
-                       static_cast<const int*>(nullptr), dig);
-  } else {
-    if (!part) return hipErrorInvalidValue;
-    const long Rp = static_cast<long>(T) * EMU_TILE;
-    hipLaunchKernelGGL(emu_rowexp_rc, dim3((nr + 255) / 256, nkb), dim3(256), 0, s, op, r0, r1, part, Rp);
-    hipLaunchKernelGGL((emu_split<EMU_S, false>), dim3(t1 - t0, nkb), dim3(256), 0, s, op, T, t0, ex,
-                       static_cast<const int*>(part), dig);
-  }
-  return hipGetLastError();
-}
-
-// Entries of the exponent array of an operand with R rows.
-inline size_t emu_scale_count(long R) { return static_cast<size_t>((R + EMU_TILE - 1) / EMU_TILE) * EMU_TILE; }
-
-// Entries of the per-k-block exponent scratch of a rows-contiguous operand.
-inline size_t emu_part_count(long R, long K) {
-  return emu_scale_count(R) * static_cast<size_t>((K + EMU_KB - 1) / EMU_KB);
-}
 
 inline hipError_t emu_launch(const EmuGemmArgs& g, hipStream_t s) {
   if (g.ntx <= 0 || g.nty <= 0 || g.nkb <= 0) return hipSuccess;

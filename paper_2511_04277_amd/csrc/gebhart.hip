@@ -31,9 +31,9 @@
 // RAD_PREC_FP64_I8 keeps FP64 factors and the FP64 chain, but the products
 // with K = panel width (the trailing update and forward substitution of each
 // panel, the back substitution's and the transposed solves' updates) run as
-// exact int8 digit products on the int8 matrix cores (emu_kernels.h): each
-// operand is scaled per row and split into 7 digits of 7 bits, and the digit
-// products are accumulated in FP64.
+// exact int8 digit products on the int8 matrix cores (emu_kernels.h,
+// emu_split.h): each operand is scaled per row and split into 7 digits of 7
+// bits, and the digit products are accumulated in FP64.
 //
 // Adjoint: K^T = U^T L^T, so Lambda = K^{-T} G is a block forward solve with
 // U^T (diagonal blocks D_k^{-T}) followed by a block backward solve with L^T,
@@ -41,7 +41,7 @@
 // the residual G - K^T Lambda = (G - Lambda) + P^T Lambda is formed in FP64.
 #include <type_traits>
 
-#include "emu_kernels.h"
+#include "emu_split.h"
 #include "gebhart_kernels.h"
 
 namespace rad {
