@@ -159,7 +159,19 @@ agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const double* __re
     wsum += wi;
     const double* row = X + static_cast<long>(i) * ldx;
     __syncthreads();  // the previous row's gathers are done
-    for (int j = threadIdx.x; j <= n; j += AGGL_THREADS) xrow[j] = __builtin_nontemporal_load(row + j);
+    // eight loads per thread in flight (addresses clamped to the row, so no
+    // load waits behind a bounds branch)
+    for (int j0 = 0; j0 <= n; j0 += 8 * AGGL_THREADS) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = __builtin_nontemporal_load(row + min(j0 + u * AGGL_THREADS + static_cast<int>(threadIdx.x), n));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u * AGGL_THREADS + static_cast<int>(threadIdx.x);
+        if (j <= n) xrow[j] = v[u];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < HPT; ++k) {
@@ -167,7 +179,14 @@ agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const double* __re
       if (H < g) {
         const int cb = offs[H], ce = offs[H + 1];
         double sv = 0.0;
-        for (int b = cb; b < ce; ++b) sv += xrow[members[b]];
+        for (int b0 = cb; b0 < ce; b0 += 4) {  // four index loads in flight, sums in member order
+          int m[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) m[u] = members[min(b0 + u, ce - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (b0 + u < ce) sv += xrow[m[u]];
+        }
         acc[k] += wi * sv;
       } else if (H == g) {
         acc[k] += wi * xrow[n];

@@ -90,7 +90,9 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
                                               emu_v4i (*lds)[S * EMU_TILE * 4]) {
   constexpr int CH = S * EMU_TILE * 4;  // 16-byte chunks per operand block
   static_assert(2 * CH * 16 >= EMU_TILE * EMU_TILE * 8 + 2 * EMU_TILE * 4, "C block must fit the LDS");
-  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  // the wave index is uniform: the copies' addresses become a scalar base and
+  // one lane offset
+  const int t = threadIdx.x, l = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const emu_v4i* ga = reinterpret_cast<const emu_v4i*>(g.A) + static_cast<long>(by) * CH;
   const emu_v4i* gb = reinterpret_cast<const emu_v4i*>(g.B) + static_cast<long>(bx) * CH;
@@ -104,8 +106,10 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
   auto stage = [&](int kb) {
     const emu_v4i* sa = ga + kb * stride_a;
     const emu_v4i* sb = gb + kb * stride_b;
+    static_assert(CH % 256 == 0, "whole pieces per wave");
 #pragma unroll
-    for (int p = w; p < CH / 64; p += 4) {
+    for (int i = 0; i < CH / 256; ++i) {
+      const int p = w + 4 * i;
       __builtin_amdgcn_global_load_lds(sa + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[0][p * 64]), 16, 0, 0);
       __builtin_amdgcn_global_load_lds(sb + p * 64 + l, (__attribute__((address_space(3))) void*)(&lds[1][p * 64]), 16, 0, 1);
     }
@@ -176,8 +180,9 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
   // sides are zero) adds nothing to C; every wave finds the same answer and
   // leaves before copying anything.
   {
-    const int ea = g.xa[row0t + l], eb = g.xb[col0t + l];
-    if (__all(ea == EMU_EXP_NONE) || __all(eb == EMU_EXP_NONE)) return;
+    const int ea = g.xa[row0t + l], eb = g.xb[col0t + l];  // both loads in flight together
+    const bool za = __all(ea == EMU_EXP_NONE), zb = __all(eb == EMU_EXP_NONE);
+    if (za | zb) return;
   }
   stage(0);
   // the last block is peeled so that the C staging's addresses are not held
@@ -213,31 +218,40 @@ __device__ __forceinline__ void emu_gemm_tile(const EmuGemmArgs& g, int bx, int 
     }
     return;
   }
+  // edge tiles: per column block, C and the exponents with every load issued
+  // before the first is used (addresses clamped into the matrix; the padded
+  // exponent arrays cover every row and column of a tile)
+  int eav[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) eav[i][v] = g.xa[row0 + 16 * i + 4 * fc + v];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int col = col0 + 16 * j + fr;
-    int seg = 0, cc = col;
-    if (g.nseg > 1 && col >= g.N[0]) {
-      seg = 1;
-      cc = col - g.N[0];
-    }
-    if (cc >= g.N[seg] || seg >= g.nseg) continue;
+    const int seg = (g.nseg > 1 && col >= g.N[0]) ? 1 : 0;
+    const int cc = col - (seg ? g.N[0] : 0);
+    const int nseg_cols = seg ? g.N[1] : g.N[0];
+    double* Cc = (seg ? g.C[1] : g.C[0]) + min(cc, nseg_cols - 1);
+    const long ldc = seg ? g.ldc[1] : g.ldc[0];
     const int eb = g.xb[col];
-    double* Cc = g.C[seg] + cc;
-    const long ldc = g.ldc[seg];
+    double cv[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cv[i][v] = Cc[static_cast<long>(min(row0 + 16 * i + 4 * fc + v, g.M - 1)) * ldc];
+    if (seg >= g.nseg || cc >= nseg_cols) continue;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + 16 * i + 4 * fc + v;
-        if (row >= g.M) continue;
-        const int ea = g.xa[row];
-        if (ea == EMU_EXP_NONE || eb == EMU_EXP_NONE) continue;  // a zero row or column adds nothing
+        const int ea = eav[i][v];
+        if (row >= g.M || ea == EMU_EXP_NONE || eb == EMU_EXP_NONE) continue;  // a zero row or column adds nothing
         double x = 0.0;
 #pragma unroll
         for (int d = S - 1; d >= 0; --d) x = fma(static_cast<double>(ci[d][i][j][v]), ldexp(1.0, -7 * (d + 2)), x);
-        double* p = Cc + static_cast<long>(row) * ldc;
-        *p = fma(g.alpha, ldexp(x, ea + eb), *p);
+        Cc[static_cast<long>(row) * ldc] = fma(g.alpha, ldexp(x, ea + eb), cv[i][v]);
       }
   }
 }

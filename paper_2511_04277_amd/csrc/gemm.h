@@ -72,8 +72,22 @@ __device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[NBR
                                            int l) {
   const int li = l & 15;
   const bool full = (wr0 + 16 * NBR <= M) && (wc0 + 16 * NBR <= N);
+  // per row block: the C values are loaded together (addresses clamped into
+  // the matrix rather than a bounds branch per element, which would make
+  // every load wait for the one before it), then fused and stored
 #pragma unroll
-  for (int rb = 0; rb < NBR; ++rb)
+  for (int rb = 0; rb < NBR; ++rb) {
+    T cv[NBR][4] = {};
+    if (g.beta != T(0)) {
+#pragma unroll
+      for (int cb = 0; cb < NBR; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = min(wr0 + rb * 16 + Mfma<T>::orow(l, r), M - 1);
+          const int j = min(wc0 + cb * 16 + li, N - 1);
+          cv[cb][r] = Cm[static_cast<long>(i) * ldc + j];
+        }
+    }
 #pragma unroll
     for (int cb = 0; cb < NBR; ++cb)
 #pragma unroll
@@ -82,11 +96,11 @@ __device__ __forceinline__ void store_tile(const typename Mfma<T>::v4 (&acc)[NBR
         const int j = wc0 + cb * 16 + li;
         if (full || (i < M && j < N)) {
           // one explicit fused form, so every tile shape rounds alike
-          T* p = Cm + static_cast<long>(i) * ldc + j;
           const T ax = g.alpha * acc[rb][cb][r];
-          *p = g.beta != T(0) ? fma(g.beta, *p, ax) : ax;
+          Cm[static_cast<long>(i) * ldc + j] = g.beta != T(0) ? fma(g.beta, cv[cb][r], ax) : ax;
         }
       }
+  }
 }
 
 // The workgroup stages each TS x KC slab of op(A) and KC x TS slab of B
