@@ -302,10 +302,25 @@ vf_fraction_lds(const double* __restrict__ F, long ldf, int nf, const int* __res
     const int a = members[m];
     const double* frow = F + static_cast<long>(a) * ldf;
     double* rrow = R + static_cast<long>(a) * ldr;
-    for (int b = threadIdx.x; b <= nf; b += blockDim.x) {
-      const int H = b < nf ? group[b] : g;
-      const double den = (H >= 0 && H <= g) ? drow[H] : 0.0;
-      rrow[b] = den != 0.0 ? __builtin_nontemporal_load(frow + b) / den : 0.0;
+    // eight columns per thread with their loads in flight together
+    // (addresses clamped into the row; selects on computed values only)
+    for (int b0 = 0; b0 <= nf; b0 += 8 * 256) {
+      int hv[8];
+      double fv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = min(b0 + u * 256 + static_cast<int>(threadIdx.x), nf);
+        hv[u] = group[min(b, nf - 1)];
+        fv[u] = __builtin_nontemporal_load(frow + b);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + u * 256 + static_cast<int>(threadIdx.x);
+        if (b > nf) break;
+        const int H = b < nf ? hv[u] : g;
+        const double den = (H >= 0 && H <= g) ? drow[H] : 0.0;
+        rrow[b] = den != 0.0 ? fv[u] / den : 0.0;
+      }
     }
   }
 }
@@ -318,8 +333,12 @@ ne_ratio(const double* __restrict__ num, const double* __restrict__ den, long ld
   const int H = blockIdx.x * 256 + threadIdx.x;
   if (H > g) return;
   for (int G = blockIdx.y; G < g; G += gridDim.y) {
+    // both loads in flight together: the select is marked unpredictable, so
+    // the quotient (and its load) is not moved behind a branch on d
     const double d = den[static_cast<long>(G) * ldd + H];
-    E[static_cast<long>(G) * lde + H] = d != 0.0 ? num[static_cast<long>(G) * ldd + H] / d : we[G] / ws[G];
+    const double q = num[static_cast<long>(G) * ldd + H];
+    const double r = q / d, mean = we[G] / ws[G];
+    E[static_cast<long>(G) * lde + H] = __builtin_unpredictable(d != 0.0) ? r : mean;
   }
 }
 

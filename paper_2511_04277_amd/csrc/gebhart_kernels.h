@@ -761,7 +761,17 @@ template <class T>
 __global__ void __launch_bounds__(256)
 copy_rows(const T* __restrict__ src, long lds, T* __restrict__ dst, long ldd, int cols) {
   const long i = blockIdx.x;
-  for (int j = threadIdx.x; j < cols; j += blockDim.x) dst[i * ldd + j] = src[i * lds + j];
+  // eight loads per thread in flight (addresses clamped into the row)
+  for (int j0 = threadIdx.x; j0 < cols; j0 += 8 * blockDim.x) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[i * lds + min(j0 + u * static_cast<int>(blockDim.x), cols - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * static_cast<int>(blockDim.x);
+      if (j < cols) dst[i * ldd + j] = v[u];
+    }
+  }
 }
 
 // dst rows [0, rows) <- src, NB columns; 16 rows per workgroup, each thread
@@ -781,8 +791,16 @@ template <class S, class D>
 __global__ void __launch_bounds__(256)
 copy_block(const S* __restrict__ src, long lds, int n, D* __restrict__ dst, long ldd) {
   const int i = blockIdx.x;
-  for (int j = threadIdx.x; j <= n; j += blockDim.x)
-    dst[static_cast<long>(i) * ldd + j] = static_cast<D>(src[static_cast<long>(i) * lds + j]);
+  for (int j0 = threadIdx.x; j0 <= n; j0 += 8 * blockDim.x) {  // eight loads per thread in flight
+    S v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[static_cast<long>(i) * lds + min(j0 + u * static_cast<int>(blockDim.x), n)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * static_cast<int>(blockDim.x);
+      if (j <= n) dst[static_cast<long>(i) * ldd + j] = static_cast<D>(v[u]);
+    }
+  }
 }
 
 // max of v over a 256-thread block, merged into *target with one atomic per
@@ -855,13 +873,22 @@ load_rhs(const double* __restrict__ G, long ldg, int n, T* __restrict__ Y, long 
   const int i = blockIdx.x;
   T* y = Y + static_cast<long>(i) * ldy;
   int bad = 0;
-  for (long j = threadIdx.x; j < ldy; j += blockDim.x) {
-    double v = 0.0;
-    if (j <= n && i < n) {
-      v = G[static_cast<long>(i) * ldg + j];
-      bad |= !(fabs(v) <= 1.0e300);
+  // eight loads per thread in flight: addresses clamped into G, entries
+  // outside its n x (n + 1) range replaced by zero afterwards
+  const long gi = static_cast<long>(min(i, n - 1)) * ldg;
+  for (long j0 = threadIdx.x; j0 < ldy; j0 += 8 * blockDim.x) {
+    double g[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) g[u] = G[gi + min(j0 + u * static_cast<long>(blockDim.x), static_cast<long>(n))];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long j = j0 + u * static_cast<long>(blockDim.x);
+      if (j >= ldy) break;
+      const bool in = j <= n && i < n;
+      const double v = __builtin_unpredictable(in) ? g[u] : 0.0;
+      bad |= in && !(fabs(v) <= 1.0e300);
+      y[j] = static_cast<T>(v);
     }
-    y[j] = static_cast<T>(v);
   }
   if (bad) raise_status(&sc->status, RAD_ENONFINITE);
 }
