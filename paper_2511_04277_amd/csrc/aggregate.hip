@@ -27,7 +27,7 @@ constexpr int AGG_THREADS = 256;
 __global__ void __launch_bounds__(CSR_CHUNK)
 csr_rank(const int* __restrict__ group, int n, int g, int* __restrict__ rank, int* __restrict__ cnt,
          int* __restrict__ status) {
-  __shared__ int chunk[CSR_CHUNK];
+  __shared__ __align__(16) int chunk[CSR_CHUNK];
   const int c = blockIdx.x, tid = threadIdx.x;
   const int i = c * CSR_CHUNK + tid;
   int gi = i < n ? group[i] : -1;
@@ -38,57 +38,76 @@ csr_rank(const int* __restrict__ group, int n, int g, int* __restrict__ rank, in
   chunk[tid] = gi;
   __syncthreads();
   if (gi < 0) return;
+  // equal ids before tid in the chunk; the loop bound (a multiple of 64) is
+  // the same for every lane of a wave (no divergence), four ids per LDS read
+  // and four reads in flight
+  const int qend = (tid | 63) + 1;
   int r = 0;
-#pragma unroll 8
-  for (int q = 0; q < tid; ++q) r += (chunk[q] == gi);
-  bool last = true;
-  for (int q = tid + 1; q < CSR_CHUNK; ++q)
-    if (chunk[q] == gi) {
-      last = false;
-      break;
+  for (int q0 = 0; q0 < qend; q0 += 16) {
+    int4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const int4*>(&chunk[q0 + 4 * u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 4 * u;
+      r += (v[u].x == gi && q < tid) + (v[u].y == gi && q + 1 < tid) + (v[u].z == gi && q + 2 < tid) +
+           (v[u].w == gi && q + 3 < tid);
     }
+  }
   rank[i] = r;
-  if (last) cnt[static_cast<long>(c) * g + gi] = r + 1;
+  atomicMax(&cnt[static_cast<long>(c) * g + gi], r + 1);  // the chunk's count of gi (cnt starts at zero)
 }
 
 // one block: cnt (nch x g, zero where a group is absent from a chunk) becomes
-// the chunk offsets in place; offs[G] = sum of the counts of groups < G
+// the chunk offsets in place; offs[G] = sum of the counts of groups < G.
+// Thread t takes the groups G = t, t + 1024, ... (coalesced), eight chunk
+// counts in flight at a time; the group totals are scanned by the block in
+// rounds of 1024 groups.
 __global__ void __launch_bounds__(1024)
 csr_offsets(int* __restrict__ cnt, int nch, int g, int* __restrict__ offs, int* __restrict__ status) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
-  const int per = (g + 1023) / 1024;
-  const int g0 = tid * per, g1 = min(g, g0 + per);
-  int sum = 0;
-  for (int G = g0; G < g1; ++G) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry = 0;
+  for (int G0 = 0; G0 < g; G0 += 1024) {
+    const int G = G0 + tid;
     int run = 0;
-    for (int c = 0; c < nch; ++c) {
-      const int v = cnt[static_cast<long>(c) * g + G];
-      cnt[static_cast<long>(c) * g + G] = run;
-      run += v;
+    if (G < g) {
+      for (int c0 = 0; c0 < nch; c0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cnt[static_cast<long>(min(c0 + u, nch - 1)) * g + G];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < nch) {
+            cnt[static_cast<long>(c0 + u) * g + G] = run;
+            run += v[u];
+          }
+      }
+      if (run == 0) atomicMin(status, RAD_EINVAL);  // empty group
     }
-    if (run == 0) atomicMin(status, RAD_EINVAL);  // empty group
-    offs[G] = run;  // total for now
-    sum += run;
-  }
-  part[tid] = sum;
-  __syncthreads();
-  if (tid == 0) {  // exclusive scan over the 1024 thread totals
-    int run = 0;
-    for (int q = 0; q < 1024; ++q) {
-      const int v = part[q];
-      part[q] = run;
-      run += v;
+    int x = run;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off);
+      if (lane >= off) x += y;
     }
-    offs[g] = run;
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (tid < 64) {  // inclusive scan of the 16 wave totals
+      int t = tid < 16 ? wsum[tid] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const int y = __shfl_up(t, off);
+        if (lane >= off) t += y;
+      }
+      if (tid < 16) wsum[tid] = t;
+    }
+    __syncthreads();
+    if (G < g) offs[G] = carry + (wv > 0 ? wsum[wv - 1] : 0) + x - run;
+    carry += wsum[15];
+    __syncthreads();  // wsum is rewritten in the next round
   }
-  __syncthreads();
-  int run = part[tid];
-  for (int G = g0; G < g1; ++G) {
-    const int v = offs[G];
-    offs[G] = run;
-    run += v;
-  }
+  if (tid == 0) offs[g] = carry;
 }
 
 __global__ void __launch_bounds__(256)
