@@ -516,7 +516,7 @@ def cpu_baseline_timing(oracle, inst, f_enf, b_ref, g_host, iters: int, n1: int,
       column), a warm-up and the median of 3 runs, scaled by the entry count
       N (N+1) / (m (m+1)) (the oracle's iteration is elementwise array work,
       linear in the entries once the arrays exceed the caches: 269 ns per
-      entry at m = 4096 against 251 at the full size on the GPU machine's host,
+      entry at m = 4096 against 251 at the full size on a 16-thread MI355X host,
       while m = 2048 fits in cache at 80) and by the GPU run's iteration count;
     * REF solve: the full-size LU solve, median of 3 (its warm-up is the
       accuracy check run just before);
