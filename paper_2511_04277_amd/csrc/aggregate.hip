@@ -160,22 +160,38 @@ agg_reduce(const double* __restrict__ X, long ldx, int n, const double* __restri
 constexpr int AGGL_THREADS = 512;
 constexpr size_t AGGL_MAX_LDS = 150 * 1024;
 
-template <int HPT>
+// One or two weightings of the same sums (NWT): the column-group sums
+// sum_{j in H} X_ij are formed once per member row and enter both outputs,
+// each in the same order and with the same rounding as a call of its own.
+struct AggOut {
+  const double* w[2];  // per-row weights
+  double* Y[2];        // g x (g+1) outputs
+  double* gw[2];       // group weights (nullable)
+};
+
+template <int HPT, int NWT>
 __global__ void __launch_bounds__(AGGL_THREADS)
-agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const double* __restrict__ w,
-               const int* __restrict__ offs, const int* __restrict__ members, int g,
-               double* __restrict__ Y, long ldy, double* __restrict__ gw, int divide) {
+agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const int* __restrict__ offs,
+               const int* __restrict__ members, int g, AggOut o, long ldy, int divide) {
   extern __shared__ double xrow[];  // n + 1
   const int G = blockIdx.x;
   const int rb = offs[G], re = offs[G + 1];
-  double acc[HPT];
+  double acc[NWT][HPT];
 #pragma unroll
-  for (int k = 0; k < HPT; ++k) acc[k] = 0.0;
-  double wsum = 0.0;
+  for (int t = 0; t < NWT; ++t)
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) acc[t][k] = 0.0;
+  double wsum[NWT];
+#pragma unroll
+  for (int t = 0; t < NWT; ++t) wsum[t] = 0.0;
   for (int a = rb; a < re; ++a) {
     const int i = members[a];
-    const double wi = w[i];
-    wsum += wi;
+    double wi[NWT];
+#pragma unroll
+    for (int t = 0; t < NWT; ++t) {
+      wi[t] = o.w[t][i];
+      wsum[t] += wi[t];
+    }
     const double* row = X + static_cast<long>(i) * ldx;
     __syncthreads();  // the previous row's gathers are done
     // eight loads per thread in flight (addresses clamped to the row, so no
@@ -206,23 +222,30 @@ agg_reduce_lds(const double* __restrict__ X, long ldx, int n, const double* __re
           for (int u = 0; u < 4; ++u)
             if (b0 + u < ce) sv += xrow[m[u]];
         }
-        acc[k] += wi * sv;
+#pragma unroll
+        for (int t = 0; t < NWT; ++t) acc[t][k] += wi[t] * sv;
       } else if (H == g) {
-        acc[k] += wi * xrow[n];
+#pragma unroll
+        for (int t = 0; t < NWT; ++t) acc[t][k] += wi[t] * xrow[n];
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < HPT; ++k) {
-    const int H = threadIdx.x + k * AGGL_THREADS;
-    if (H <= g) Y[static_cast<long>(G) * ldy + H] = divide ? acc[k] / wsum : acc[k];
+  for (int t = 0; t < NWT; ++t) {
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int H = threadIdx.x + k * AGGL_THREADS;
+      if (H <= g) o.Y[t][static_cast<long>(G) * ldy + H] = divide ? acc[t][k] / wsum[t] : acc[t][k];
+    }
+    if (o.gw[t] && threadIdx.x == 0) o.gw[t][G] = wsum[t];
   }
-  if (gw && threadIdx.x == 0) gw[G] = wsum;
 }
 
-// agg_reduce_lds when the row fits in LDS and the outputs in registers, else agg_reduce
-void launch_agg(const double* X, long ldx, int n, const double* w, const int* offs, const int* members, int g,
-                double* Y, long ldy, double* gw, int divide, hipStream_t s) {
+// agg_reduce_lds when the row fits in LDS and the outputs in registers, else
+// agg_reduce (once per weighting)
+template <int NWT>
+void launch_agg_n(const double* X, long ldx, int n, const AggOut& o, const int* offs, const int* members, int g,
+                  long ldy, int divide, hipStream_t s) {
   const size_t lds = static_cast<size_t>(n + 1) * sizeof(double);
   const int hpt = (g + AGGL_THREADS) / AGGL_THREADS;  // ceil((g + 1) / AGGL_THREADS)
   if (lds <= AGGL_MAX_LDS && hpt <= 32) {
@@ -231,25 +254,32 @@ void launch_agg(const double* X, long ldx, int n, const double* w, const int* of
       return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(AGGL_MAX_LDS)) ==
              hipSuccess;
     };
-    const void* fn = hpt <= 4    ? reinterpret_cast<const void*>(&agg_reduce_lds<4>)
-                     : hpt <= 16 ? reinterpret_cast<const void*>(&agg_reduce_lds<16>)
-                                 : reinterpret_cast<const void*>(&agg_reduce_lds<32>);
+    const void* fn = hpt <= 4    ? reinterpret_cast<const void*>(&agg_reduce_lds<4, NWT>)
+                     : hpt <= 16 ? reinterpret_cast<const void*>(&agg_reduce_lds<16, NWT>)
+                                 : reinterpret_cast<const void*>(&agg_reduce_lds<32, NWT>);
     if (lds <= 64 * 1024 || allow(fn)) {
       if (hpt <= 4)
-        hipLaunchKernelGGL(agg_reduce_lds<4>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx, n,
-                           w, offs, members, g, Y, ldy, gw, divide);
+        hipLaunchKernelGGL((agg_reduce_lds<4, NWT>), dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X,
+                           ldx, n, offs, members, g, o, ldy, divide);
       else if (hpt <= 16)
-        hipLaunchKernelGGL(agg_reduce_lds<16>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx,
-                           n, w, offs, members, g, Y, ldy, gw, divide);
+        hipLaunchKernelGGL((agg_reduce_lds<16, NWT>), dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X,
+                           ldx, n, offs, members, g, o, ldy, divide);
       else
-        hipLaunchKernelGGL(agg_reduce_lds<32>, dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X, ldx,
-                           n, w, offs, members, g, Y, ldy, gw, divide);
+        hipLaunchKernelGGL((agg_reduce_lds<32, NWT>), dim3(static_cast<unsigned>(g)), dim3(AGGL_THREADS), lds, s, X,
+                           ldx, n, offs, members, g, o, ldy, divide);
       return;
     }
     (void)hipGetLastError();  // the attribute was refused: the gather form below
   }
   dim3 grid(static_cast<unsigned>(ceil_div(g + 1, AGG_THREADS)), static_cast<unsigned>(g));
-  hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, ldx, n, w, offs, members, g, Y, ldy, gw, divide);
+  for (int t = 0; t < NWT; ++t)
+    hipLaunchKernelGGL(agg_reduce, grid, dim3(AGG_THREADS), 0, s, X, ldx, n, o.w[t], offs, members, g, o.Y[t], ldy,
+                       o.gw[t], divide);
+}
+
+void launch_agg(const double* X, long ldx, int n, const double* w, const int* offs, const int* members, int g,
+                double* Y, long ldy, double* gw, int divide, hipStream_t s) {
+  launch_agg_n<1>(X, ldx, n, AggOut{{w, nullptr}, {Y, nullptr}, {gw, nullptr}}, offs, members, g, ldy, divide, s);
 }
 
 __global__ void __launch_bounds__(256) zero_ints(int* __restrict__ p, long count) {
@@ -394,6 +424,13 @@ void agg_sums(const double* X, long ldx, int n, const double* w, const AggLayout
               double* gw, hipStream_t s) {
   ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
   launch_agg(X, ldx, n, w, l.offs, l.members, g, Y, ldy, gw, 0, s);
+}
+
+// the same sums under two weightings in one pass over X
+void agg_sums2(const double* X, long ldx, int n, const double* w0, const double* w1, const AggLayout& l, int g,
+               double* Y0, double* Y1, long ldy, double* gw0, double* gw1, hipStream_t s) {
+  ProfScope prof(s, RAD_PROF_AGGREGATE, 0.0, 8.0 * static_cast<double>(n) * (n + 1));
+  launch_agg_n<2>(X, ldx, n, AggOut{{w0, w1}, {Y0, Y1}, {gw0, gw1}}, l.offs, l.members, g, ldy, 0, s);
 }
 
 int read_status(const int* dev, hipStream_t s, int* out) {
@@ -562,8 +599,7 @@ extern "C" int32_t rad_node_emissivity(const double* B, int64_t nf, int64_t ldb,
   agg_build(group, ni, gi, t.agg, s);
   hipLaunchKernelGGL(face_weights, dim3(static_cast<unsigned>(ceil_div(nf, 256))), dim3(256), 0, s, eps, area, ni,
                      t.w, t.agg.status);
-  agg_sums(B, static_cast<long>(ldb), ni, t.w, t.agg, gi, t.d0, t.ldd, t.gw0, s);
-  agg_sums(B, static_cast<long>(ldb), ni, area, t.agg, gi, t.d1, t.ldd, t.gw1, s);
+  agg_sums2(B, static_cast<long>(ldb), ni, t.w, area, t.agg, gi, t.d0, t.d1, t.ldd, t.gw0, t.gw1, s);
   hipLaunchKernelGGL(ne_ratio, dim3(static_cast<unsigned>(ceil_div(g + 1, 256)), static_cast<unsigned>(std::min<int64_t>(g, 32768))), dim3(256),
                      0, s, t.d0, t.d1, t.ldd, t.gw0, t.gw1, gi, E, static_cast<long>(lde));
   RAD_HIP_CHECK(hipGetLastError());
